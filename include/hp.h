@@ -1,0 +1,145 @@
+/*
+ * hp.h -- C ABI of the RbmSAT block-Gibbs hot path on MI355X (gfx950).
+ *
+ * The method (Sec. 3 of "Solving MaxSAT with Matrix Multiplication"): a CNF
+ * formula becomes a product of clause-RBMs (Sec. 3.1), one canonical OR-gate
+ * RBM (W_c, b_c) per temperature mapped onto every clause by the negation
+ * transform (eq. 4); B parallel Markov chains then run block Gibbs sampling
+ * (eqs. 2-3, factorised as eqs. 6-7) and keep the best assignment seen
+ * (Sec. 3.2).  One sweep, per chain: gather the clause inputs, count the
+ * satisfied clauses, track the best, sample the hidden units of every clause,
+ * scatter-add the per-clause logit contributions onto the variables, update
+ * the conditional-variance moving average (Sec. 3.4) and sample new values.
+ *
+ * Conventions
+ *   - Every function returns an hp_status (0 = success, < 0 = error); no C++
+ *     exception crosses this boundary.  hp_last_error() returns a message for
+ *     the last failure on the calling thread.
+ *   - "host" pointers are read during the call only and may be freed when it
+ *     returns; "device" pointers are HIP device memory owned by the caller.
+ *   - Streams are hipStream_t passed as void*; NULL is the null stream.  All
+ *     device work is enqueued on that stream; nothing synchronises the host.
+ *   - A batch may hold several formulas of different sizes.  Formula f has
+ *     N_f = var_offset[f+1]-var_offset[f] variables and
+ *     C_f = clause_offset[f+1]-clause_offset[f] clauses, and B chains.  Its
+ *     per-chain arrays occupy the [B][N_f] row-major block starting at element
+ *     var_offset[f]*B of the batch-wide arrays.
+ */
+#ifndef HP_H
+#define HP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HP_OK = 0,
+    HP_EINVAL = -1,        /* invalid argument; nothing was allocated or enqueued */
+    HP_ENOMEM = -2,        /* device allocation failed                            */
+    HP_EDEVICE = -3,       /* a HIP runtime call failed                           */
+    HP_EUNSUPPORTED = -4   /* valid input outside what this build handles         */
+} hp_status;
+
+typedef enum {
+    HP_FP64 = 0,           /* logits, sigmoid and variance EMA in FP64            */
+    HP_FP32 = 1,           /* the same in FP32 (tables prepared in FP64)          */
+    HP_MIXED_BF16 = 2      /* reserved: BF16-limb MFMA contraction                */
+} hp_precision;
+
+/* The formula batch: signed 1-based literal table (Sec. 3.3).  Column c of
+ * lits lists the literals of clause c; the sign is the polarity, so the
+ * column (1, 2, -3, 4) is v1 or v2 or (not v3) or v4.  A 0 entry is padding
+ * (Sec. 3.1) and is replaced by the clause's first non-zero literal, i.e.
+ * the clause is padded by repeating a literal with the same polarity
+ * (Sec. 3.3), which keeps its satisfying set. */
+typedef struct {
+    int32_t n_formulas;             /* F >= 1                                          */
+    const int64_t *var_offset;      /* host [F+1], prefix sums of N_f, var_offset[0]=0 */
+    const int64_t *clause_offset;   /* host [F+1], prefix sums of C_f                  */
+    int32_t k;                      /* padded clause width K, 1..7                     */
+    const int32_t *lits;            /* host [K][sum C_f], clause-minor; literals of
+                                       formula f are 1-based within that formula      */
+} hp_cnf;
+
+/* Canonical OR-gate RBMs, one per temperature (Sec. 3.1 "OR gate as an
+ * RBM", the free-energy target F* acts as the temperature; appendix
+ * "Pretraining": L = 3 for K = 3, L = K+1 for K in [4,7]).  The visible bias
+ * is zero (Sec. 3.1). */
+typedef struct {
+    int32_t k, l, n_temps;          /* K (must equal hp_cnf.k), L in 1..8, n_temps >= 1 */
+    const double *W;                /* host [n_temps][K][L]  canonical weights W_c     */
+    const double *b;                /* host [n_temps][L]     canonical hidden bias b_c */
+} hp_rbm;
+
+typedef struct {
+    int32_t chains;                 /* B chains per formula (the "batch size"), >= 1   */
+    const int32_t *temp_of_chain;   /* host [B] temperature index per chain, or NULL:
+                                       chain b uses floor(b*n_temps/B)                 */
+    int32_t precision;              /* hp_precision                                    */
+    double alpha;                   /* variance moving-average rate, in [0, 1]         */
+    uint64_t seed;                  /* Philox key source                               */
+    int32_t threads;                /* workgroup size override (0 = automatic)         */
+    int32_t split;                  /* workgroups per chain override (0 = automatic)   */
+} hp_opts;
+
+/* Chain state: caller-owned DEVICE buffers in the layout described above.
+ * The randomness of sweep t comes from Philox4x32-10 (Salmon et al., SC'11)
+ * with key (seed mod 2^32, (seed div 2^32) xor f) and counter
+ * (t mod 2^32, chain, phase*2^31 + block, t div 2^32): hidden unit l of
+ * clause c uses block c*ceil(L/4) + l/4 of phase 0, visible unit i uses block
+ * i/4 of phase 1, and word j%4 of the block becomes U = (word >> 8) * 2^-24;
+ * a unit is set iff U < its conditional probability.  Because draws are
+ * addressed by the absolute sweep t, hp_run(S1) followed by hp_run(S2)
+ * equals hp_run(S1+S2) bit for bit. */
+typedef struct {
+    uint8_t *v;                     /* device [sum N_f * B] current assignment, 0/1     */
+    void *nu;                       /* device [sum N_f * B] variance EMA: double for
+                                       HP_FP64, float for HP_FP32                       */
+    int32_t *s_max;                 /* device [F*B] best satisfied-clause count         */
+    uint8_t *best;                  /* device [sum N_f * B] assignment achieving s_max  */
+    int64_t *t;                     /* device [1] absolute sweep counter                */
+    int64_t total_vars;             /* sum N_f the buffers were sized for (checked)     */
+    int32_t n_formulas;             /* F the buffers were sized for (checked)           */
+    int32_t chains;                 /* B the buffers were sized for (checked)           */
+    int32_t nu_bytes;               /* sizeof(*nu): 8 or 4 (checked against precision)  */
+} hp_state;
+
+typedef struct hp_plan_s *hp_plan_t;
+
+/* Build a plan (formula-RBM assembly, Sec. 3.1 and eq. 4): validates the
+ * batch, copies every host array, uploads the packed clause table, the
+ * per-variable occurrence lists and the per-temperature tables, and enqueues
+ * the table preparation on `stream`.  The plan owns its device memory until
+ * hp_free.  Errors (HP_EINVAL, nothing allocated): K outside 1..7, L outside
+ * 1..8 or rbm->k != cnf->k, N_f < 1 or C_f < 1, a literal with |lit| > N_f,
+ * an all-zero clause, non-finite weights, alpha outside [0,1], chains < 1, a
+ * temperature index outside [0, n_temps).  HP_EUNSUPPORTED: N_f > 32768, or
+ * a formula whose working set exceeds the workgroup's LDS. */
+hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
+                  const hp_opts *opts, void *stream);
+
+/* Enqueue n_sweeps >= 0 block-Gibbs rounds on every chain of every formula
+ * (the inner loop of Sec. 3.2; 500 rounds per dispatch in the appendix
+ * "Batching operations").  Each round first counts the satisfied clauses of
+ * the current assignment and, on a strict improvement, records it in s_max
+ * and best; n_sweeps = 0 performs only that count-and-track step.  *t is
+ * advanced by n_sweeps.  HP_EINVAL if the state does not match the plan. */
+hp_status hp_run(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
+
+/* Release a plan's device memory (synchronises the device first).  NULL is
+ * accepted. */
+hp_status hp_free(hp_plan_t plan);
+
+/* Static description of a status code. */
+const char *hp_status_string(hp_status s);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *hp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HP_H */
