@@ -1,0 +1,300 @@
+// C-ABI entry points: validation, formula-RBM assembly (packing of the clause
+// table and the per-variable occurrence lists), device allocation and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hp_internal.hpp"
+
+namespace hp {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+hp_status fail(hp_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+hp_status hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? HP_ENOMEM : HP_EDEVICE;
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src, hipStream_t s) {
+    *dst = nullptr;
+    if (src.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    // src is kept alive by the caller until the copy completes (synchronised
+    // at the end of hp_plan), so an asynchronous copy is safe
+    return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+void release(Plan *p) {
+    if (!p) return;
+    (void)hipFree(p->d_fd);
+    (void)hipFree(p->d_work);
+    (void)hipFree(p->d_lits);
+    (void)hipFree(p->d_csr_ptr);
+    (void)hipFree(p->d_occ);
+    (void)hipFree(p->d_temp);
+    (void)hipFree(p->d_W);
+    (void)hipFree(p->d_b);
+    (void)hipFree(p->tab.thr);
+    (void)hipFree(p->tab.g64);
+    (void)hipFree(p->tab.g32);
+    delete p;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+}  // namespace hp
+
+using namespace hp;
+
+extern "C" {
+
+const char *hp_status_string(hp_status s) {
+    switch (s) {
+        case HP_OK: return "HP_OK";
+        case HP_EINVAL: return "HP_EINVAL: invalid argument";
+        case HP_ENOMEM: return "HP_ENOMEM: device allocation failed";
+        case HP_EDEVICE: return "HP_EDEVICE: HIP runtime error";
+        case HP_EUNSUPPORTED: return "HP_EUNSUPPORTED: outside what this build handles";
+    }
+    return "unknown hp_status";
+}
+
+const char *hp_last_error(void) { return g_last_error.c_str(); }
+
+hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp_opts *opts,
+                  void *stream) {
+    g_last_error.clear();
+    if (!out || !cnf || !rbm || !opts) return fail(HP_EINVAL, "null argument");
+    *out = nullptr;
+    const int F = cnf->n_formulas;
+    const int K = cnf->k;
+    if (F < 1) return fail(HP_EINVAL, "n_formulas must be >= 1");
+    if (K < 1 || K > kMaxK) return fail(HP_EINVAL, "K must be in 1..7");
+    if (rbm->k != K) return fail(HP_EINVAL, "rbm.k must equal cnf.k");
+    const int L = rbm->l;
+    if (L < 1 || L > kMaxL) return fail(HP_EINVAL, "L must be in 1..8");
+    const int T = rbm->n_temps;
+    if (T < 1) return fail(HP_EINVAL, "n_temps must be >= 1");
+    if (!cnf->var_offset || !cnf->clause_offset || !cnf->lits || !rbm->W || !rbm->b)
+        return fail(HP_EINVAL, "null array");
+    const int B = opts->chains;
+    if (B < 1) return fail(HP_EINVAL, "chains must be >= 1");
+    if (!(opts->alpha >= 0.0 && opts->alpha <= 1.0)) return fail(HP_EINVAL, "alpha must be in [0,1]");
+    if (opts->precision == HP_MIXED_BF16)
+        return fail(HP_EUNSUPPORTED, "mixed BF16 precision is not available in this build");
+    if (opts->precision != HP_FP64 && opts->precision != HP_FP32)
+        return fail(HP_EINVAL, "unknown precision");
+    if (opts->threads != 0 && (opts->threads < kWave || opts->threads > 1024 || opts->threads % kWave))
+        return fail(HP_EINVAL, "threads must be 0 or a multiple of 64 in [64, 1024]");
+    for (int i = 0; i < T * K * L; ++i)
+        if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
+    for (int i = 0; i < T * L; ++i)
+        if (!std::isfinite(rbm->b[i])) return fail(HP_EINVAL, "non-finite bias");
+    std::vector<int32_t> temp(B);
+    for (int b = 0; b < B; ++b) {
+        temp[b] = opts->temp_of_chain ? opts->temp_of_chain[b] : (int32_t)((int64_t)b * T / B);
+        if (temp[b] < 0 || temp[b] >= T) return fail(HP_EINVAL, "temperature index out of range");
+    }
+    if (cnf->var_offset[0] != 0 || cnf->clause_offset[0] != 0)
+        return fail(HP_EINVAL, "offsets must start at 0");
+    int max_n = 0, max_c = 0;
+    for (int f = 0; f < F; ++f) {
+        const int64_t n = cnf->var_offset[f + 1] - cnf->var_offset[f];
+        const int64_t c = cnf->clause_offset[f + 1] - cnf->clause_offset[f];
+        if (n < 1 || c < 1) return fail(HP_EINVAL, "every formula needs N_f >= 1 and C_f >= 1");
+        if (n > kMaxVars) return fail(HP_EUNSUPPORTED, "N_f above 32768");
+        if (c >= (int64_t(1) << 28)) return fail(HP_EUNSUPPORTED, "C_f too large");
+        max_n = std::max<int>(max_n, (int)n);
+        max_c = std::max<int>(max_c, (int)c);
+    }
+    const int64_t NV = cnf->var_offset[F], NC = cnf->clause_offset[F];
+    if ((int64_t)K * NC >= (int64_t(1) << 32)) return fail(HP_EUNSUPPORTED, "too many clause slots");
+
+    // --- clause table: padding normalisation + packing (idx | neg << 15) ---
+    std::vector<uint16_t> lits((size_t)K * NC);
+    std::vector<uint32_t> deg(NV, 0);
+    for (int f = 0; f < F; ++f) {
+        const int64_t n = cnf->var_offset[f + 1] - cnf->var_offset[f];
+        for (int64_t c = cnf->clause_offset[f]; c < cnf->clause_offset[f + 1]; ++c) {
+            int32_t first = 0;
+            for (int k = 0; k < K; ++k)
+                if (cnf->lits[(size_t)k * NC + c] != 0) {
+                    first = cnf->lits[(size_t)k * NC + c];
+                    break;
+                }
+            if (first == 0) return fail(HP_EINVAL, "clause " + std::to_string(c) + " has no literal");
+            for (int k = 0; k < K; ++k) {
+                int32_t x = cnf->lits[(size_t)k * NC + c];
+                if (x == 0) x = first;
+                const int64_t a = x < 0 ? -(int64_t)x : (int64_t)x;
+                if (a > n) return fail(HP_EINVAL, "literal " + std::to_string(x) + " exceeds N_f");
+                lits[(size_t)k * NC + c] = (uint16_t)((a - 1) | (x < 0 ? 0x8000u : 0u));
+                deg[cnf->var_offset[f] + a - 1]++;
+            }
+        }
+    }
+    // --- per-variable occurrence lists, (c, k) ascending ---
+    std::vector<uint32_t> csr_ptr(NV + F);
+    std::vector<uint32_t> occ((size_t)K * NC);
+    {
+        uint64_t pos = 0;
+        for (int f = 0; f < F; ++f) {
+            const int64_t v0 = cnf->var_offset[f], n = cnf->var_offset[f + 1] - v0;
+            for (int64_t i = 0; i < n; ++i) {
+                csr_ptr[v0 + f + i] = (uint32_t)pos;
+                pos += deg[v0 + i];
+            }
+            csr_ptr[v0 + f + n] = (uint32_t)pos;
+        }
+        std::vector<uint32_t> fill(NV + F);
+        for (int64_t i = 0; i < NV + F; ++i) fill[i] = csr_ptr[i];
+        for (int f = 0; f < F; ++f) {
+            const int64_t v0 = cnf->var_offset[f], c0 = cnf->clause_offset[f];
+            for (int64_t c = c0; c < cnf->clause_offset[f + 1]; ++c)
+                for (int k = 0; k < K; ++k) {
+                    const uint16_t e = lits[(size_t)k * NC + c];
+                    const int64_t slot = v0 + f + (e & 0x7fff);
+                    occ[fill[slot]++] = ((uint32_t)(c - c0) << 4) | ((e >> 15) << 3) | (uint32_t)k;
+                }
+        }
+    }
+    // --- formula descriptors and the work list (largest formulas first) ---
+    std::vector<FormulaDev> fd(F);
+    for (int f = 0; f < F; ++f) {
+        fd[f].n = (int32_t)(cnf->var_offset[f + 1] - cnf->var_offset[f]);
+        fd[f].c = (int32_t)(cnf->clause_offset[f + 1] - cnf->clause_offset[f]);
+        fd[f].var_off = cnf->var_offset[f];
+        fd[f].clause_off = cnf->clause_offset[f];
+        fd[f].ptr_off = cnf->var_offset[f] + f;
+    }
+    std::vector<int> order(F);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)fd[a].n * 7 + fd[a].c > (int64_t)fd[b].n * 7 + fd[b].c;
+    });
+    std::vector<WorkItem> work;
+    work.reserve((size_t)F * B);
+    for (int f : order)
+        for (int b = 0; b < B; ++b) work.push_back({f, b});
+
+    // --- launch shape and LDS budget ---
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return fail(HP_ENOMEM, "host allocation failed");
+    p->F = F; p->K = K; p->L = L; p->T = T; p->B = B;
+    p->precision = opts->precision;
+    p->alpha = opts->alpha;
+    p->seed = opts->seed;
+    p->total_vars = NV; p->total_clauses = NC; p->total_occ = (int64_t)K * NC;
+    p->max_n = max_n; p->max_c = max_c;
+    p->n_work = (int32_t)work.size();
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+    const size_t real_bytes = opts->precision == HP_FP64 ? 8 : 4;
+    int threads = opts->threads;
+    if (threads == 0) threads = 1024;
+    int groups = (max_n + 3) / 4;
+    int vpt = (groups + threads - 1) / threads;
+    int vpt_pow = 1;
+    while (vpt_pow < vpt) vpt_pow *= 2;
+    if (vpt_pow > 32) { release(p); return fail(HP_EUNSUPPORTED, "too many variables per thread"); }
+    p->threads = threads;
+    p->vpt = vpt_pow;
+    size_t off = (size_t)kPatterns * kMaxL * 4 + (size_t)kHidMasks * kMaxL * real_bytes + 64 * 4;
+    p->lds_v_off = (int32_t)off;
+    off += round_up((size_t)max_n, 16);
+    p->lds_hm_off = (int32_t)off;
+    off += round_up((size_t)max_c, 16);
+    p->lds_bytes = off;
+    if ((int64_t)off > max_lds) {
+        release(p);
+        return fail(HP_EUNSUPPORTED, "formula working set (" + std::to_string(off) +
+                                         " B) exceeds the workgroup LDS limit (" +
+                                         std::to_string(max_lds) + " B)");
+    }
+
+    // --- device upload ---
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> Wv(rbm->W, rbm->W + (size_t)T * K * L), bv(rbm->b, rbm->b + (size_t)T * L);
+#define HP_TRY(expr, what)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) {                             \
+            (void)hipStreamSynchronize(s);                  \
+            release(p);                                     \
+            return hip_fail(e_, what);                      \
+        }                                                   \
+    } while (0)
+    HP_TRY(upload(&p->d_fd, fd, s), "upload formulas");
+    HP_TRY(upload(&p->d_work, work, s), "upload work list");
+    HP_TRY(upload(&p->d_lits, lits, s), "upload clause table");
+    HP_TRY(upload(&p->d_csr_ptr, csr_ptr, s), "upload occurrence offsets");
+    HP_TRY(upload(&p->d_occ, occ, s), "upload occurrences");
+    HP_TRY(upload(&p->d_temp, temp, s), "upload temperatures");
+    HP_TRY(upload(&p->d_W, Wv, s), "upload W_c");
+    HP_TRY(upload(&p->d_b, bv, s), "upload b_c");
+    HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kPatterns * kMaxL * sizeof(uint32_t)), "alloc thr");
+    HP_TRY(hipMalloc((void **)&p->tab.g64, (size_t)T * kHidMasks * kMaxL * sizeof(double)), "alloc g64");
+    HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
+    HP_TRY(launch_tables(*p, s), "table kernel");
+    // host staging vectors go out of scope below: wait for the copies
+    HP_TRY(hipStreamSynchronize(s), "plan upload");
+#undef HP_TRY
+    *out = reinterpret_cast<hp_plan_t>(p);
+    return HP_OK;
+}
+
+hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !st) return fail(HP_EINVAL, "null argument");
+    if (n_sweeps < 0) return fail(HP_EINVAL, "n_sweeps must be >= 0");
+    if (!st->v || !st->nu || !st->s_max || !st->best || !st->t) return fail(HP_EINVAL, "null state buffer");
+    if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B)
+        return fail(HP_EINVAL, "state shape does not match the plan");
+    const int want = p->precision == HP_FP64 ? 8 : 4;
+    if (st->nu_bytes != want) return fail(HP_EINVAL, "nu element size does not match the precision");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != p->device) return fail(HP_EINVAL, "plan was built on another device");
+    e = launch_sweep(*p, *st, n_sweeps, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    return HP_OK;
+}
+
+hp_status hp_free(hp_plan_t plan) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p) return HP_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    hipError_t e = hipDeviceSynchronize();
+    release(p);
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    return HP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of ``libhp.so`` (the C ABI declared in include/hp.h).
+
+Argument marshalling only: every step of the sweep runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  The library must
+have been built (``python -m paper_2311_02101_amd.build``); loading fails
+loudly otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhp.so")
+
+HP_OK, HP_EINVAL, HP_ENOMEM, HP_EDEVICE, HP_EUNSUPPORTED = 0, -1, -2, -3, -4
+HP_FP64, HP_FP32, HP_MIXED_BF16 = 0, 1, 2
+PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
+
+EXPORTS = ("hp_plan", "hp_run", "hp_free", "hp_status_string", "hp_last_error")
+
+
+class HpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class HpCnf(ct.Structure):
+    _fields_ = [("n_formulas", ct.c_int32), ("var_offset", ct.POINTER(ct.c_int64)),
+                ("clause_offset", ct.POINTER(ct.c_int64)), ("k", ct.c_int32),
+                ("lits", ct.POINTER(ct.c_int32))]
+
+
+class HpRbm(ct.Structure):
+    _fields_ = [("k", ct.c_int32), ("l", ct.c_int32), ("n_temps", ct.c_int32),
+                ("W", ct.POINTER(ct.c_double)), ("b", ct.POINTER(ct.c_double))]
+
+
+class HpOpts(ct.Structure):
+    _fields_ = [("chains", ct.c_int32), ("temp_of_chain", ct.POINTER(ct.c_int32)),
+                ("precision", ct.c_int32), ("alpha", ct.c_double), ("seed", ct.c_uint64),
+                ("threads", ct.c_int32), ("split", ct.c_int32)]
+
+
+class HpState(ct.Structure):
+    _fields_ = [("v", ct.c_void_p), ("nu", ct.c_void_p), ("s_max", ct.c_void_p),
+                ("best", ct.c_void_p), ("t", ct.c_void_p), ("total_vars", ct.c_int64),
+                ("n_formulas", ct.c_int32), ("chains", ct.c_int32), ("nu_bytes", ct.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2311_02101_amd.build` (no CPU fallback exists)")
+    # Bind to the HIP runtime PyTorch already carries: torch loads its own
+    # libamdhip64 (soname libamdhip64.so.7) by path, so importing it first
+    # makes libhp.so's dependency resolve to that same copy.  Two runtimes in
+    # one process would not share devices or streams.
+    import torch  # noqa: F401
+    lib = ct.CDLL(LIB_PATH)
+    lib.hp_plan.argtypes = [ct.POINTER(ct.c_void_p), ct.POINTER(HpCnf), ct.POINTER(HpRbm),
+                            ct.POINTER(HpOpts), ct.c_void_p]
+    lib.hp_plan.restype = ct.c_int
+    lib.hp_run.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
+    lib.hp_run.restype = ct.c_int
+    lib.hp_free.argtypes = [ct.c_void_p]
+    lib.hp_free.restype = ct.c_int
+    lib.hp_status_string.argtypes = [ct.c_int]
+    lib.hp_status_string.restype = ct.c_char_p
+    lib.hp_last_error.argtypes = []
+    lib.hp_last_error.restype = ct.c_char_p
+    _lib = lib
+    return lib
+
+
+def device_available() -> bool:
+    import torch
+    return torch.cuda.is_available()
+
+
+def _check(status):
+    if status != HP_OK:
+        lib = load()
+        raise HpError(status, f"{lib.hp_status_string(status).decode()}: "
+                              f"{lib.hp_last_error().decode()}")
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ct.POINTER(ctype))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A planned formula batch (``hp_plan``); call ``run`` with a ``State``.
+
+    tables: list of per-formula signed 1-based [K][C_f] literal tables.
+    n_vars: list of N_f.  W: [T][K][L], b: [T][L] canonical OR-gate RBMs."""
+
+    def __init__(self, tables, n_vars, W, b, *, chains, temps=None, precision="f64",
+                 alpha=1e-3, seed=0, threads=0, split=0, stream=None):
+        lib = load()
+        tables = [np.asarray(t, dtype=np.int32) for t in tables]
+        n_vars = [int(n) for n in n_vars]
+        K = tables[0].shape[0]
+        if any(t.shape[0] != K for t in tables):
+            raise ValueError("all formulas must share the padded width K")
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(-1, K, np.shape(W)[-1]))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(W.shape[0], W.shape[2]))
+        self.K, self.L, self.T = K, W.shape[2], W.shape[0]
+        self.F, self.B = len(tables), int(chains)
+        self.n_vars = n_vars
+        self.n_clauses = [t.shape[1] for t in tables]
+        self.var_offset = np.concatenate([[0], np.cumsum(n_vars)]).astype(np.int64)
+        self.clause_offset = np.concatenate([[0], np.cumsum(self.n_clauses)]).astype(np.int64)
+        self.lits = np.ascontiguousarray(np.concatenate(tables, axis=1), dtype=np.int32)
+        self.precision = precision
+        cnf = HpCnf(self.F, _ptr(self.var_offset, ct.c_int64), _ptr(self.clause_offset, ct.c_int64),
+                    K, _ptr(self.lits, ct.c_int32))
+        rbm = HpRbm(K, self.L, self.T, _ptr(W, ct.c_double), _ptr(b, ct.c_double))
+        tp = None
+        if temps is not None:
+            self.temps = np.ascontiguousarray(temps, dtype=np.int32)
+            if self.temps.shape != (self.B,):
+                raise ValueError("temps must have one entry per chain")
+            tp = _ptr(self.temps, ct.c_int32)
+        opts = HpOpts(self.B, tp, PRECISION[precision], float(alpha), int(seed) & (2 ** 64 - 1),
+                      int(threads), int(split))
+        h = ct.c_void_p()
+        _check(lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts),
+                           _stream_handle(stream)))
+        self._h = h
+
+    @property
+    def total_vars(self):
+        return int(self.var_offset[-1])
+
+    def new_state(self, v0_list, device="cuda"):
+        """Allocate a device state from per-formula [B][N_f] initial assignments
+        (nu = 0.25, s_max = 0, best = v0, t = 0)."""
+        return State.from_host(self, v0_list, device)
+
+    def run(self, state, n_sweeps, stream=None):
+        lib = load()
+        _check(lib.hp_run(self._h, ct.byref(state.c_struct()), int(n_sweeps),
+                          _stream_handle(stream)))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().hp_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class State:
+    """Device chain state (torch tensors) in the layout of include/hp.h."""
+
+    def __init__(self, plan, v, nu, s_max, best, t):
+        self.plan, self.v, self.nu, self.s_max, self.best, self.t = plan, v, nu, s_max, best, t
+
+    @classmethod
+    def from_host(cls, plan, v0_list, device="cuda"):
+        import torch
+        flat = np.concatenate([np.asarray(v, dtype=np.uint8).reshape(-1) for v in v0_list])
+        if flat.size != plan.total_vars * plan.B:
+            raise ValueError("initial states do not match the plan's sizes")
+        ndt = torch.float64 if plan.precision == "f64" else torch.float32
+        v = torch.from_numpy(flat.copy()).to(device)
+        nu = torch.full((flat.size,), 0.25, dtype=ndt, device=device)
+        s_max = torch.zeros(plan.F * plan.B, dtype=torch.int32, device=device)
+        best = v.clone()
+        t = torch.zeros(1, dtype=torch.int64, device=device)
+        return cls(plan, v, nu, s_max, best, t)
+
+    def c_struct(self):
+        p = self.plan
+        return HpState(self.v.data_ptr(), self.nu.data_ptr(), self.s_max.data_ptr(),
+                       self.best.data_ptr(), self.t.data_ptr(), p.total_vars, p.F, p.B,
+                       self.nu.element_size())
+
+    def formula(self, f):
+        """Host copies (v, nu, s_max, best) of formula f as [B][N_f] arrays."""
+        p = self.plan
+        a, n = int(p.var_offset[f]) * p.B, p.n_vars[f]
+        sl = slice(a, a + n * p.B)
+        return (self.v[sl].cpu().numpy().reshape(p.B, n),
+                self.nu[sl].cpu().numpy().reshape(p.B, n),
+                self.s_max[f * p.B:(f + 1) * p.B].cpu().numpy().astype(np.int64),
+                self.best[sl].cpu().numpy().reshape(p.B, n))
+
+    def set_formula(self, f, v=None, nu=None, s_max=None, best=None):
+        import torch
+        p = self.plan
+        a, n = int(p.var_offset[f]) * p.B, p.n_vars[f]
+        sl = slice(a, a + n * p.B)
+        dev = self.v.device
+        if v is not None:
+            self.v[sl] = torch.from_numpy(np.ascontiguousarray(v, dtype=np.uint8).reshape(-1)).to(dev)
+        if nu is not None:
+            self.nu[sl] = torch.from_numpy(np.ascontiguousarray(nu).reshape(-1)).to(dev, self.nu.dtype)
+        if s_max is not None:
+            self.s_max[f * p.B:(f + 1) * p.B] = torch.from_numpy(
+                np.asarray(s_max, dtype=np.int32)).to(dev)
+        if best is not None:
+            self.best[sl] = torch.from_numpy(np.ascontiguousarray(best, dtype=np.uint8).reshape(-1)).to(dev)
+
+    def set_t(self, t):
+        self.t.fill_(int(t))
+
+    def get_t(self):
+        return int(self.t.item())

@@ -1,0 +1,243 @@
+"""HIP path vs the CPU FP64 oracle, through the C ABI (``libhp.so``).
+
+Every case prints its name, sizes and seed before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from oracle import rbmsat as R
+from paper_2311_02101_amd import workload as wl
+from tests.parity import compare_state, say, teacher_forced_sweep
+
+pytestmark = pytest.mark.gpu
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _trajectory(hip, tables, ns, W, b, B, S, prec, seed, alpha=1e-3, temps=None,
+                chains=None, formulas=None, threads=0, label=""):
+    """Run S sweeps on the GPU and on the oracle (for the listed formulas and
+    chains); compare final states exactly.  On a mismatch, replay with
+    teacher forcing and require every difference to be a flagged tie."""
+    from paper_2311_02101_amd import hp
+    temps = wl.default_temperatures(B, W.shape[0]) if temps is None else np.asarray(temps)
+    say(f"[{label}] plan F={len(tables)} N={list(ns)[:6]} B={B} S={S} prec={prec} seed={seed}")
+    plan = hp.Plan(tables, ns, W, b, chains=B, temps=temps, precision=prec, alpha=alpha,
+                   seed=seed, threads=threads)
+    v0s = [wl.initial_state(B, n, seed, tag=f) for f, n in enumerate(ns)]
+    st = plan.new_state(v0s)
+    say(f"[{label}] gpu run")
+    plan.run(st, S)
+    _sync()
+    assert st.get_t() == S
+    chains = np.arange(B) if chains is None else np.asarray(chains)
+    formulas = range(len(tables)) if formulas is None else formulas
+    for f in formulas:
+        op = R.plan(tables[f], ns[f], W, b)
+        ost = R.initial(v0s[f][chains])
+        R.run(ost, op, temps[chains], S, alpha=alpha, seed=seed, formula_id=f, chain_ids=chains)
+        gv, gnu, gs, gbest = st.formula(f)
+        got = (gv[chains], gnu[chains], gs[chains], gbest[chains])
+        try:
+            compare_state(got, (ost.v, ost.nu, ost.s_max, ost.best), prec, f"{label} f={f}")
+        except AssertionError as err:
+            say(f"[{label}] f={f}: trajectory mismatch ({err}); replaying with teacher forcing")
+            # replay the whole run sweep by sweep on a fresh plan of this formula
+            sub = hp.Plan([tables[f]], [ns[f]], W, b, chains=B, temps=temps, precision=prec,
+                          alpha=alpha, seed=seed, threads=threads)
+            sst = sub.new_state([v0s[f]])
+            o2 = R.initial(v0s[f])
+            ties = 0
+            for _ in range(S):
+                ties += teacher_forced_sweep(sub, sst, 0, o2, op, temps, alpha=alpha, seed=seed,
+                                             prec=prec)
+            say(f"[{label}] f={f}: {ties} flagged ties over {S} sweeps")
+            assert ties > 0, "trajectory mismatch without any tie"
+    plan.free()
+    return st
+
+
+# --------------------------------------------------------------------------
+# Plain method, smallest: N = 256, 1 chain, FP64, seed 0 -- 500-sweep trajectory
+# --------------------------------------------------------------------------
+def test_plain_n256_b1_fp64_trajectory(hip):
+    w = wl.config_workload("plain_n256_b1")
+    _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 1, 500, "f64", w.seed, label="n256 fp64")
+
+
+def test_plain_n256_b1_fp32_teacher_forced(hip):
+    from paper_2311_02101_amd import hp
+    w = wl.config_workload("plain_n256_b1")
+    say("[n256 fp32] teacher forced 40 sweeps")
+    plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=1, temps=w.temps, precision="f32",
+                   seed=w.seed)
+    st = plan.new_state(w.v0)
+    op = R.plan(w.tables[0], 256, w.W, w.b)
+    ost = R.initial(w.v0[0])
+    for _ in range(40):
+        teacher_forced_sweep(plan, st, 0, ost, op, w.temps, alpha=1e-3, seed=w.seed, prec="f32")
+
+
+# --------------------------------------------------------------------------
+# Plain method, medium: N = 4096, 64 chains, seed 1 (the benchmark's launch)
+# --------------------------------------------------------------------------
+def test_plain_n4096_b64_fp64_sampled_chains(hip):
+    w = wl.config_workload("plain_n4096_b64")
+    _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 64, 40, "f64", w.seed,
+                chains=[0, 1, 31, 32, 62, 63], label="n4096 fp64")
+
+
+def test_plain_n4096_b64_fp32_teacher_forced_all_chains(hip):
+    from paper_2311_02101_amd import hp
+    w = wl.config_workload("plain_n4096_b64", precision="f32")
+    say("[n4096 fp32] teacher forced, 64 chains x 2 sweeps")
+    plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps, precision="f32",
+                   seed=w.seed)
+    st = plan.new_state(w.v0)
+    plan.run(st, 25)             # move away from the initial state first
+    _sync()
+    v, nu, s_max, best = st.formula(0)
+    op = R.plan(w.tables[0], 4096, w.W, w.b)
+    ost = R.State(v, nu.astype(np.float64), s_max, best, 25)
+    ties = 0
+    for _ in range(2):
+        ties += teacher_forced_sweep(plan, st, 0, ost, op, w.temps, alpha=1e-3, seed=w.seed,
+                                     prec="f32")
+    say(f"[n4096 fp32] flagged ties: {ties}")
+
+
+# --------------------------------------------------------------------------
+# Larger shapes of the measured configurations, on sampled chains / formulas
+# --------------------------------------------------------------------------
+def test_n8192_b256_fp64_sampled_chains(hip):
+    w = wl.config_workload("mixed_n8192_b256", precision="f64")
+    _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 256, 6, "f64", w.seed,
+                chains=[0, 127, 128, 255], label="n8192 fp64")
+
+
+def test_uneven_batch_sampled_formulas(hip):
+    sizes = wl.uneven_sizes(1024, 3)[:48]
+    tables = [wl.random_formula(int(n), 3, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    order = np.argsort(sizes)
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    _trajectory(hip, tables, [int(n) for n in sizes], W, b, 8, 12, "f64", 3,
+                chains=[0, 7], formulas=pick, label="uneven fp64")
+
+
+def test_uneven_batch_fp32_sampled_formulas(hip):
+    from paper_2311_02101_amd import hp
+    sizes = [64, 5000, 300, 16384, 77]
+    tables = [wl.random_formula(int(n), 3, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    temps = wl.default_temperatures(4, 2)
+    say("[uneven fp32] teacher forced on every formula")
+    plan = hp.Plan(tables, sizes, W, b, chains=4, temps=temps, precision="f32", seed=3)
+    st = plan.new_state([wl.initial_state(4, n, 3, tag=f) for f, n in enumerate(sizes)])
+    for f, n in enumerate(sizes):
+        v, nu, s_max, best = st.formula(f)
+        op = R.plan(tables[f], n, W, b)
+        ost = R.State(v, nu.astype(np.float64), s_max, best, 0)
+        teacher_forced_sweep(plan, st, f, ost, op, temps, alpha=1e-3, seed=3, prec="f32")
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+def test_launch_shapes_agree(hip, threads):
+    """Register-resident (1, 4 groups/thread) and global-memory EMA paths."""
+    n = 4096
+    T = wl.random_formula(n, 21)
+    W, b = wl.gaussian_rbm(2, 7, 8, 21)
+    _trajectory(hip, [T], [n], W, b, 3, 8, "f64", 21, threads=threads, label=f"threads={threads}")
+
+
+def test_tiny_and_ragged_formulas(hip):
+    clauses = [[[1]], [[1, -2], [2]], [[3, -1, 2], [-3]], [[-4, 1], [2, 3, 4], [-1, -2, -3]],
+               [[5, -1, 2], [-3, 4], [1], [-5, 2, 3]]]
+    ns = [1, 2, 3, 4, 5]
+    tables = [wl.pad_clauses(cl, 3) for cl in clauses]
+    W, b = wl.gaussian_rbm(1, 3, 3, 4)
+    _trajectory(hip, tables, ns, W, b, 5, 30, "f64", 4, label="tiny K=3 L=3")
+
+
+def test_zero_padded_literals_are_normalised(hip):
+    n = 40
+    T = wl.random_formula(n, 13, ratio=3)
+    Tz = T.copy()
+    for c in range(T.shape[1]):
+        L = len(set(T[:, c]))
+        Tz[L:, c] = 0                 # trailing padding written as zeros
+    W, b = wl.gaussian_rbm(2, 7, 8, 13)
+    from paper_2311_02101_amd import hp
+    say("[zero padding] plans from zero-padded and repeated tables")
+    st = []
+    for tab in (T, Tz):
+        plan = hp.Plan([tab], [n], W, b, chains=4, precision="f64", seed=13)
+        s = plan.new_state([wl.initial_state(4, n, 13)])
+        plan.run(s, 20)
+        st.append(s.formula(0))
+    _sync()
+    for a, c in zip(*st):
+        assert np.array_equal(a, c)
+
+
+def test_resume_and_count_only(hip):
+    from paper_2311_02101_amd import hp
+    n = 700
+    T = wl.random_formula(n, 5)
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    v0 = wl.initial_state(6, n, 5)
+    say("[resume] run(12) vs run(7)+run(0)+run(5)")
+    p = hp.Plan([T], [n], W, b, chains=6, precision="f64", seed=5)
+    a = p.new_state([v0])
+    c = p.new_state([v0])
+    p.run(a, 12)
+    p.run(c, 7)
+    p.run(c, 0)
+    p.run(c, 5)
+    _sync()
+    for x, y in zip(a.formula(0), c.formula(0)):
+        assert np.array_equal(x, y)
+    assert a.get_t() == c.get_t() == 12
+    # a zero-sweep run counts the current state (s_max, best) and keeps t
+    d = p.new_state([v0])
+    p.run(d, 0)
+    _sync()
+    v, nu, s_max, best = d.formula(0)
+    op = R.plan(T, n, W, b)
+    assert np.array_equal(s_max, R.clause_count(v0, op))
+    assert np.array_equal(best, v0) and d.get_t() == 0 and np.all(nu == 0.25)
+
+
+def test_stationary_distribution_on_gpu(hip):
+    """The device sampler's long-run distribution is p(v) ~ exp(-F_f(v))."""
+    from paper_2311_02101_amd import hp
+    n = 5
+    T = wl.pad_clauses([[1, -2], [2, 3, -4], [-5, 1, 2], [4, -1], [3, 5]], 3)
+    rng = np.random.default_rng(8)
+    W_c, b_c = 0.8 * rng.standard_normal((1, 3, 3)), 0.8 * rng.standard_normal((1, 3))
+    op = R.plan(T, n, W_c, b_c)
+    Wf, bf = R.dense_formula_rbm(op)
+    V = ((np.arange(2 ** n)[:, None] >> np.arange(n)[None, :]) & 1).astype(float)
+    F = R.free_energy(V, Wf, bf)
+    pi = np.exp(-(F - F.min()))
+    pi /= pi.sum()
+    B = 8192
+    say(f"[stationarity] B={B}")
+    plan = hp.Plan([T], [n], W_c, b_c, chains=B, precision="f64", seed=77, threads=64)
+    st = plan.new_state([wl.initial_state(B, n, 77)])
+    plan.run(st, 100)
+    counts = np.zeros(2 ** n)
+    code = 1 << np.arange(n)
+    for _ in range(60):
+        plan.run(st, 5)
+        v = st.formula(0)[0].astype(np.int64)
+        counts += np.bincount(v @ code, minlength=2 ** n)
+    tv = 0.5 * np.abs(counts / counts.sum() - pi).sum()
+    say(f"[stationarity] TV = {tv:.4f}")
+    assert tv < 0.01
