@@ -25,12 +25,13 @@ if ROOT not in sys.path:
 # ---------------------------------------------------------------------------
 # ALU cost model of one chain-sweep (K = 7, L = 8, C = 6N):
 #   Philox4x32-10 calls: C * ceil(L/4) hidden + ceil(N/4) visible
-#   one call = 10 rounds x (2 v_mad_u64_u32 at 4 issue slots + 4 v_xor_b32)
-#            = 120 VALU lane-slots
+#   one call = 10 rounds x (2 v_mad_u64_u32 + 4 v_xor_b32) = 60 VALU
+#            instructions, each one issue slot per lane (a Philox-only loop
+#            measures 55 lane-slots per call on MI355X at the rated clock)
 #   each Bernoulli draw adds a shift and an unsigned compare (2 slots)
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-slots/s.
 # ---------------------------------------------------------------------------
-PHILOX_SLOTS = 120
+PHILOX_SLOTS = 60
 DRAW_SLOTS = 2
 PEAK_SLOTS = 256 * 64 * 2.4e9
 
@@ -50,6 +51,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="plain_n4096_b64")
     ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "push", "pull"])
     ap.add_argument("--cpu-sweeps", type=int, default=10,
                     help="sweeps of the oracle sample (all chains); 0 skips the CPU leg")
     args = ap.parse_args(argv)
@@ -70,7 +72,8 @@ def main(argv=None):
     C = w.tables[0].shape[1]
     L = w.W.shape[2]
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=B, temps=w.temps,
-                   precision=args.precision, alpha=w.alpha, seed=w.seed, threads=args.threads)
+                   precision=args.precision, alpha=w.alpha, seed=w.seed, threads=args.threads,
+                   kernel=args.kernel)
     st = plan.new_state(w.v0, device=dev)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -103,12 +106,14 @@ def main(argv=None):
         "dtype": args.precision, "data": "synthetic",
         "config": {"workload": args.workload, "n_vars": N, "clauses": C, "K": 7, "L": L,
                    "chains": B, "sweeps_per_step": args.sweeps, "temperatures": list(wl.FSTAR_PAIR),
-                   "threads": plan_threads(args.threads), "parallelism": "single GPU"},
+                   "threads": plan_threads(args.threads), "kernel": args.kernel,
+                   "parallelism": "single GPU"},
         "chain_sweeps_per_s": B * args.sweeps * instances / wall,
         "draws_per_s": draws * B * args.sweeps * instances / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / PEAK_SLOTS,
-                     "traffic": None, "kernel": "sweep_kernel",
+                     "traffic": None,
+                     "kernel": "sweep_pull_kernel" if args.kernel == "pull" else "sweep_push_kernel",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "philox_calls_per_chain_sweep": calls, "draws_per_chain_sweep": draws},
     }

@@ -82,7 +82,16 @@ typedef struct {
     uint64_t seed;                  /* Philox key source                               */
     int32_t threads;                /* workgroup size override (0 = automatic)         */
     int32_t split;                  /* workgroups per chain override (0 = automatic)   */
+    int32_t kernel;                 /* hp_kernel: sweep kernel variant                 */
 } hp_opts;
+
+typedef enum {
+    HP_KERNEL_AUTO = 0,             /* fixed-point push when it fits in LDS, else pull */
+    HP_KERNEL_PULL = 1,             /* per-variable occurrence lists, FP sums in the
+                                       order (clause, position) ascending             */
+    HP_KERNEL_PUSH = 2              /* clause-side scatter into int64 fixed-point LDS
+                                       accumulators (exact, order-independent sums)   */
+} hp_kernel;
 
 /* Chain state: caller-owned DEVICE buffers in the layout described above.
  * The randomness of sweep t comes from Philox4x32-10 (Salmon et al., SC'11)

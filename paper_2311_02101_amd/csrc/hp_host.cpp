@@ -48,6 +48,10 @@ void release(Plan *p) {
     (void)hipFree(p->d_lits);
     (void)hipFree(p->d_csr_ptr);
     (void)hipFree(p->d_occ);
+    (void)hipFree(p->d_rec);
+    (void)hipFree(p->d_orig);
+    (void)hipFree(p->tab.gfx);
+    (void)hipFree(p->tab.gpad);
     (void)hipFree(p->d_temp);
     (void)hipFree(p->d_W);
     (void)hipFree(p->d_b);
@@ -104,6 +108,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         return fail(HP_EINVAL, "unknown precision");
     if (opts->threads != 0 && (opts->threads < kWave || opts->threads > 1024 || opts->threads % kWave))
         return fail(HP_EINVAL, "threads must be 0 or a multiple of 64 in [64, 1024]");
+    if (opts->kernel < HP_KERNEL_AUTO || opts->kernel > HP_KERNEL_PUSH)
+        return fail(HP_EINVAL, "unknown kernel variant");
     for (int i = 0; i < T * K * L; ++i)
         if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
     for (int i = 0; i < T * L; ++i)
@@ -176,7 +182,52 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
                 }
         }
     }
-    // --- formula descriptors and the work list (largest formulas first) ---
+    // --- push-kernel clause records: length, padding merge, sort by length ---
+    // len = K minus the trailing run of copies of literal 0 (the padding of
+    // Sec. 3.3); positions >= len contribute through the merged slot 0.
+    std::vector<uint4> rec(NC);
+    std::vector<uint32_t> orig(NC);
+    std::vector<uint32_t> push_slots(NV, 0);
+    for (int f = 0; f < F; ++f) {
+        const int64_t c0 = cnf->clause_offset[f], c1 = cnf->clause_offset[f + 1];
+        std::vector<std::pair<int, int64_t>> key;
+        key.reserve(c1 - c0);
+        for (int64_t c = c0; c < c1; ++c) {
+            int len = K;
+            while (len > 1 && lits[(size_t)(len - 1) * NC + c] == lits[c]) --len;
+            key.push_back({len, c});
+            for (int k = 0; k < len; ++k) push_slots[cnf->var_offset[f] + (lits[(size_t)k * NC + c] & 0x7fff)]++;
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<int, int64_t> &a, const std::pair<int, int64_t> &b) {
+                             return a.first < b.first;
+                         });
+        for (int64_t j = 0; j < c1 - c0; ++j) {
+            const int len = key[j].first;
+            const int64_t c = key[j].second;
+            uint16_t sl[8] = {0, 0, 0, 0, 0, 0, 0, (uint16_t)len};
+            for (int k = 0; k < K; ++k) sl[k] = lits[(size_t)k * NC + c];
+            rec[c0 + j] = make_uint4(sl[0] | ((uint32_t)sl[1] << 16), sl[2] | ((uint32_t)sl[3] << 16),
+                                     sl[4] | ((uint32_t)sl[5] << 16), sl[6] | ((uint32_t)sl[7] << 16));
+            orig[c0 + j] = (uint32_t)(c - c0);
+        }
+    }
+    // fixed-point scale: every slot contributes at most Wsum = sum |W_c| in
+    // magnitude, a variable has at most max_slots slots, so |x| * 2^S stays
+    // below 2^62 when (bound + 1) * 2^S < 2^62
+    double wsum = 0.0;
+    for (int t = 0; t < T; ++t) {
+        double s = 0.0;
+        for (int i = 0; i < K * L; ++i) s += std::fabs(rbm->W[(size_t)t * K * L + i]);
+        wsum = std::max(wsum, s);
+    }
+    uint32_t max_slots = 1;
+    for (int64_t i = 0; i < NV; ++i) max_slots = std::max(max_slots, push_slots[i]);
+    const double bound = wsum * (double)max_slots * (1.0 + 1e-9) + 8.0;
+    int fx_shift = 52;
+    while (fx_shift > 0 && std::ldexp(bound + 1.0, fx_shift) >= std::ldexp(1.0, 62)) --fx_shift;
+
+    // --- formula descriptors ---
     std::vector<FormulaDev> fd(F);
     for (int f = 0; f < F; ++f) {
         fd[f].n = (int32_t)(cnf->var_offset[f + 1] - cnf->var_offset[f]);
@@ -185,17 +236,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         fd[f].clause_off = cnf->clause_offset[f];
         fd[f].ptr_off = cnf->var_offset[f] + f;
     }
-    std::vector<int> order(F);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (int64_t)fd[a].n * 7 + fd[a].c > (int64_t)fd[b].n * 7 + fd[b].c;
-    });
-    std::vector<WorkItem> work;
-    work.reserve((size_t)F * B);
-    for (int f : order)
-        for (int b = 0; b < B; ++b) work.push_back({f, b});
 
-    // --- launch shape and LDS budget ---
     Plan *p = new (std::nothrow) Plan();
     if (!p) return fail(HP_ENOMEM, "host allocation failed");
     p->F = F; p->K = K; p->L = L; p->T = T; p->B = B;
@@ -204,34 +245,65 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     p->seed = opts->seed;
     p->total_vars = NV; p->total_clauses = NC; p->total_occ = (int64_t)K * NC;
     p->max_n = max_n; p->max_c = max_c;
-    p->n_work = (int32_t)work.size();
+    p->fx_shift = fx_shift;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
     int max_lds = 0;
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
     const size_t real_bytes = opts->precision == HP_FP64 ? 8 : 4;
-    int threads = opts->threads;
-    if (threads == 0) threads = 1024;
-    int groups = (max_n + 3) / 4;
-    int vpt = (groups + threads - 1) / threads;
-    int vpt_pow = 1;
-    while (vpt_pow < vpt) vpt_pow *= 2;
-    if (vpt_pow > 32) { release(p); return fail(HP_EUNSUPPORTED, "too many variables per thread"); }
+    const int threads = opts->threads ? opts->threads : kMaxThreads;
     p->threads = threads;
-    p->vpt = vpt_pow;
-    size_t off = (size_t)kPatterns * kMaxL * 4 + (size_t)kHidMasks * kMaxL * real_bytes + 64 * 4;
-    p->lds_v_off = (int32_t)off;
-    off += round_up((size_t)max_n, 16);
-    p->lds_hm_off = (int32_t)off;
-    off += round_up((size_t)max_c, 16);
-    p->lds_bytes = off;
-    if ((int64_t)off > max_lds) {
-        release(p);
-        return fail(HP_EUNSUPPORTED, "formula working set (" + std::to_string(off) +
-                                         " B) exceeds the workgroup LDS limit (" +
-                                         std::to_string(max_lds) + " B)");
+
+    // --- kernel variant per formula, work lists (largest formulas first) ---
+    std::vector<int> order(F);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)fd[a].n * 7 + fd[a].c > (int64_t)fd[b].n * 7 + fd[b].c;
+    });
+    std::vector<WorkItem> work_push, work_pull;
+    int pn = 0, qn = 0, qc = 0;   // largest N (push), largest N and C (pull)
+    for (int f : order) {
+        int32_t vo, xo, ho;
+        const bool push_ok = fx_shift >= 40 && lds_bytes_push(fd[f].n, &vo, &xo) <= (size_t)max_lds;
+        const bool pull_ok = lds_bytes_pull(fd[f].n, fd[f].c, real_bytes, &vo, &ho) <= (size_t)max_lds;
+        bool use_push;
+        if (opts->kernel == HP_KERNEL_PUSH) {
+            if (!push_ok) {
+                release(p);
+                return fail(HP_EUNSUPPORTED, "push kernel: formula " + std::to_string(f) +
+                                                 " does not fit in LDS (" + std::to_string(max_lds) + " B)");
+            }
+            use_push = true;
+        } else if (opts->kernel == HP_KERNEL_PULL) {
+            use_push = false;
+        } else {
+            use_push = push_ok;
+        }
+        if (!use_push && !pull_ok) {
+            release(p);
+            return fail(HP_EUNSUPPORTED, "formula " + std::to_string(f) +
+                                             ": working set exceeds the workgroup LDS limit (" +
+                                             std::to_string(max_lds) + " B)");
+        }
+        for (int b = 0; b < B; ++b) (use_push ? work_push : work_pull).push_back({f, b});
+        if (use_push) pn = std::max(pn, fd[f].n);
+        else { qn = std::max(qn, fd[f].n); qc = std::max(qc, fd[f].c); }
     }
+    auto vpt_for = [&](int n) {
+        const int groups = (n + 3) / 4;
+        int v = 1;
+        while (v * threads < groups) v *= 2;
+        return v;
+    };
+    p->n_push = (int32_t)work_push.size();
+    p->vpt_push = vpt_for(pn);
+    p->vpt_pull = vpt_for(qn);
+    p->lds_push = work_push.empty() ? 0 : lds_bytes_push(pn, &p->push_v_off, &p->push_x_off);
+    p->lds_pull = work_pull.empty() ? 0 : lds_bytes_pull(qn, qc, real_bytes, &p->pull_v_off, &p->pull_hm_off);
+    std::vector<WorkItem> work(work_push);
+    work.insert(work.end(), work_pull.begin(), work_pull.end());
+    p->n_work = (int32_t)work.size();
 
     // --- device upload ---
     hipStream_t s = (hipStream_t)stream;
@@ -250,12 +322,16 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(upload(&p->d_lits, lits, s), "upload clause table");
     HP_TRY(upload(&p->d_csr_ptr, csr_ptr, s), "upload occurrence offsets");
     HP_TRY(upload(&p->d_occ, occ, s), "upload occurrences");
+    HP_TRY(upload(&p->d_rec, rec, s), "upload clause records");
+    HP_TRY(upload(&p->d_orig, orig, s), "upload clause order");
     HP_TRY(upload(&p->d_temp, temp, s), "upload temperatures");
     HP_TRY(upload(&p->d_W, Wv, s), "upload W_c");
     HP_TRY(upload(&p->d_b, bv, s), "upload b_c");
     HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kPatterns * kMaxL * sizeof(uint32_t)), "alloc thr");
     HP_TRY(hipMalloc((void **)&p->tab.g64, (size_t)T * kHidMasks * kMaxL * sizeof(double)), "alloc g64");
     HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
+    HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kMaxL * sizeof(int64_t)), "alloc gfx");
+    HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kMaxL * kHidMasks * sizeof(int64_t)), "alloc gpad");
     HP_TRY(launch_tables(*p, s), "table kernel");
     // host staging vectors go out of scope below: wait for the copies
     HP_TRY(hipStreamSynchronize(s), "plan upload");

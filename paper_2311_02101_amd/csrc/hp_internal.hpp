@@ -16,13 +16,14 @@ constexpr int kPatterns = 128;    // literal-truth patterns over K <= 7 inputs
 constexpr int kHidMasks = 256;    // hidden-state masks over L <= 8 units
 constexpr int kMaxVars = 32768;   // variable index packed in 15 bits
 constexpr int kWave = 64;
+constexpr int kMaxThreads = 1024;
 
 // Per-formula descriptor (device copy).
 struct FormulaDev {
     int32_t n;            // N_f
     int32_t c;            // C_f
     int64_t var_off;      // var_offset[f]: state block starts at var_off * B
-    int64_t clause_off;   // clause_offset[f]: column of the packed clause table
+    int64_t clause_off;   // clause_offset[f]: first clause record / column
     int64_t ptr_off;      // var_off + f: first of the N_f+1 occurrence offsets
 };
 
@@ -37,22 +38,38 @@ struct WorkItem {
 //       for the clause whose literal-truth pattern is m (eqs. 2, 4, 6);
 //   G[tau][n][k]  = sum_{l ascending, bit_l(n)} W_c[k,l]
 //       so that the contribution of clause c to its k-th input is
-//       pol_kc * G[tau][h-mask][k]  (the vector l^(c) = W_f^(c) h^(c)).
+//       pol_kc * G[tau][h-mask][k]  (the vector l^(c) = W_f^(c) h^(c));
+//   gfx[tau][n][k] = round(G * 2^S) as int64 (fixed point, scale 2^S);
+//   gpad[tau][len][n] = gfx[n][0] + sum_{k = len}^{K-1} gfx[n][k]: the
+//       merged contribution of a clause's first literal and its padding
+//       copies (Sec. 3.3 pads by repeating a literal).
 struct DeviceTables {
     uint32_t *thr = nullptr;   // [T][128][8]
     double *g64 = nullptr;     // [T][256][8]
     float *g32 = nullptr;      // [T][256][8]
+    int64_t *gfx = nullptr;    // [T][256][8]
+    int64_t *gpad = nullptr;   // [T][8][256]
 };
+
+// Clause record of the push kernel: 8 x 16-bit slots in a uint4.  Slots
+// 0..6 hold literal k as (0-based variable index) | (negated << 15); slot 7
+// holds the clause length len (positions >= len repeat literal 0).  Records
+// of a formula are sorted by len (stable); orig[] keeps the clause's index
+// in the input, which addresses its random numbers.
 
 template <typename Real>
 struct SweepParams {
     const FormulaDev *fd;
     const WorkItem *work;
-    const uint16_t *lits;        // [K][ctot]: var index (15 bits) | negated << 15
-    const uint32_t *csr_ptr;     // per formula N_f+1 absolute offsets into occ
-    const uint32_t *occ;         // (c_local << 4) | (negated << 3) | k, (c, k) ascending
+    const uint16_t *lits;        // pull: [K][ctot] var index (15 bits) | negated << 15
+    const uint32_t *csr_ptr;     // pull: per formula N_f+1 absolute offsets into occ
+    const uint32_t *occ;         // pull: (c_local << 4) | (negated << 3) | k, (c, k) ascending
+    const uint4 *rec;            // push: clause records [ctot]
+    const uint32_t *orig;        // push: input clause index [ctot]
     const uint32_t *thr;         // [T][128][8]
     const Real *G;               // [T][256][8]
+    const int64_t *gfx;          // [T][256][8]
+    const int64_t *gpad;         // [T][8][256]
     const int32_t *temp_of_chain;
     uint8_t *v;
     Real *nu;
@@ -62,12 +79,16 @@ struct SweepParams {
     int64_t ctot;
     int64_t n_sweeps;
     Real alpha;
+    double fx_scale;             // 2^-S
     uint32_t key0;
     uint32_t key1;               // xor-ed with the formula index
     int32_t K, L, B;
     int32_t lds_v_off;           // byte offsets inside dynamic LDS
-    int32_t lds_hm_off;
+    int32_t lds_hm_off;          // pull: hidden masks
+    int32_t lds_x_off;           // push: int64 accumulators
 };
+
+enum class Variant { kPull = 0, kPush = 1 };
 
 struct Plan {
     int32_t F = 0, K = 0, L = 0, T = 0, B = 0;
@@ -77,9 +98,15 @@ struct Plan {
     int64_t total_vars = 0, total_clauses = 0, total_occ = 0;
     int32_t max_n = 0, max_c = 0;
     int32_t threads = 0;
-    int32_t vpt = 0;             // visible groups of 4 per thread
-    size_t lds_bytes = 0;
-    int32_t lds_v_off = 0, lds_hm_off = 0;
+    int32_t fx_shift = 0;        // S of the fixed-point accumulators
+    // two launches: formulas whose accumulators fit in LDS use the push
+    // kernel (work items [0, n_push)), the others the pull kernel
+    // (items [n_push, n_work)); each launch is sized for its largest formula
+    int32_t n_push = 0;
+    int32_t vpt_push = 0, vpt_pull = 0;   // visible groups of 4 per thread
+    size_t lds_push = 0, lds_pull = 0;
+    int32_t push_v_off = 0, push_x_off = 0;
+    int32_t pull_v_off = 0, pull_hm_off = 0;
     int device = 0;
     // device memory
     FormulaDev *d_fd = nullptr;
@@ -87,6 +114,8 @@ struct Plan {
     uint16_t *d_lits = nullptr;
     uint32_t *d_csr_ptr = nullptr;
     uint32_t *d_occ = nullptr;
+    uint4 *d_rec = nullptr;
+    uint32_t *d_orig = nullptr;
     int32_t *d_temp = nullptr;
     double *d_W = nullptr;
     double *d_b = nullptr;
@@ -97,6 +126,10 @@ struct Plan {
 // kernels / launchers (hp_kernels.hip)
 hipError_t launch_tables(const Plan &p, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s);
+
+// LDS bytes of the two kernel variants for the largest formula
+size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);
+size_t lds_bytes_push(int max_n, int32_t *v_off, int32_t *x_off);
 
 void set_error(const std::string &msg);
 

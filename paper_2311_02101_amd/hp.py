@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libhp.so")
 HP_OK, HP_EINVAL, HP_ENOMEM, HP_EDEVICE, HP_EUNSUPPORTED = 0, -1, -2, -3, -4
 HP_FP64, HP_FP32, HP_MIXED_BF16 = 0, 1, 2
 PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
+KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
 EXPORTS = ("hp_plan", "hp_run", "hp_free", "hp_status_string", "hp_last_error")
 
@@ -42,7 +43,7 @@ class HpRbm(ct.Structure):
 class HpOpts(ct.Structure):
     _fields_ = [("chains", ct.c_int32), ("temp_of_chain", ct.POINTER(ct.c_int32)),
                 ("precision", ct.c_int32), ("alpha", ct.c_double), ("seed", ct.c_uint64),
-                ("threads", ct.c_int32), ("split", ct.c_int32)]
+                ("threads", ct.c_int32), ("split", ct.c_int32), ("kernel", ct.c_int32)]
 
 
 class HpState(ct.Structure):
@@ -113,7 +114,7 @@ class Plan:
     n_vars: list of N_f.  W: [T][K][L], b: [T][L] canonical OR-gate RBMs."""
 
     def __init__(self, tables, n_vars, W, b, *, chains, temps=None, precision="f64",
-                 alpha=1e-3, seed=0, threads=0, split=0, stream=None):
+                 alpha=1e-3, seed=0, threads=0, split=0, kernel="auto", stream=None):
         lib = load()
         tables = [np.asarray(t, dtype=np.int32) for t in tables]
         n_vars = [int(n) for n in n_vars]
@@ -140,7 +141,7 @@ class Plan:
                 raise ValueError("temps must have one entry per chain")
             tp = _ptr(self.temps, ct.c_int32)
         opts = HpOpts(self.B, tp, PRECISION[precision], float(alpha), int(seed) & (2 ** 64 - 1),
-                      int(threads), int(split))
+                      int(threads), int(split), KERNEL[kernel])
         h = ct.c_void_p()
         _check(lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts),
                            _stream_handle(stream)))

@@ -3,9 +3,12 @@
 Tolerance classes (per result):
   integer  -- clause counts, s_max, best, and every sampled bit whose margin
               |U - p| exceeds the class bound: bit-exact.
-  FP64     -- nu relative error <= 1e-13; a sampled bit may differ only where
-              |U - rho_oracle| <= 1e-12 (a flagged tie: device exp and NumPy
-              exp may differ in the last place).
+  FP64     -- nu relative error <= 1e-12; a sampled bit may differ only where
+              |U - rho_oracle| <= 3e-11 (a flagged tie).  The pull kernel sums
+              the logit x in the oracle's order (bit-identical x; only exp may
+              differ in the last place); the push kernel sums fixed-point
+              terms rounded to 2^-S with S >= 40, |dx| <= slots * 2^-(S+1)
+              <= 1e-10 even for 200 slots, so |d rho| <= 0.25 |dx|.
   FP32     -- nu relative error <= 1e-5; a sampled bit may differ only where
               |U - rho_oracle| <= 2e-6 (FP32 accumulation of at most ~100
               contributions of size <= ~10 gives |dx| <= 1e-4 * 2^-24 * 100,
@@ -17,8 +20,8 @@ import numpy as np
 
 from oracle import rbmsat as R
 
-TIE = {"f64": 1e-12, "f32": 2e-6}
-NU_RTOL = {"f64": 1e-13, "f32": 1e-5}
+TIE = {"f64": 3e-11, "f32": 2e-6}
+NU_RTOL = {"f64": 1e-12, "f32": 1e-5}
 
 
 def say(*a):

@@ -18,15 +18,16 @@ def _sync():
 
 
 def _trajectory(hip, tables, ns, W, b, B, S, prec, seed, alpha=1e-3, temps=None,
-                chains=None, formulas=None, threads=0, label=""):
+                chains=None, formulas=None, threads=0, kernel="auto", label=""):
     """Run S sweeps on the GPU and on the oracle (for the listed formulas and
     chains); compare final states exactly.  On a mismatch, replay with
     teacher forcing and require every difference to be a flagged tie."""
     from paper_2311_02101_amd import hp
     temps = wl.default_temperatures(B, W.shape[0]) if temps is None else np.asarray(temps)
-    say(f"[{label}] plan F={len(tables)} N={list(ns)[:6]} B={B} S={S} prec={prec} seed={seed}")
+    say(f"[{label}] plan F={len(tables)} N={list(ns)[:6]} B={B} S={S} prec={prec} seed={seed} "
+        f"kernel={kernel}")
     plan = hp.Plan(tables, ns, W, b, chains=B, temps=temps, precision=prec, alpha=alpha,
-                   seed=seed, threads=threads)
+                   seed=seed, threads=threads, kernel=kernel)
     v0s = [wl.initial_state(B, n, seed, tag=f) for f, n in enumerate(ns)]
     st = plan.new_state(v0s)
     say(f"[{label}] gpu run")
@@ -47,7 +48,7 @@ def _trajectory(hip, tables, ns, W, b, B, S, prec, seed, alpha=1e-3, temps=None,
             say(f"[{label}] f={f}: trajectory mismatch ({err}); replaying with teacher forcing")
             # replay the whole run sweep by sweep on a fresh plan of this formula
             sub = hp.Plan([tables[f]], [ns[f]], W, b, chains=B, temps=temps, precision=prec,
-                          alpha=alpha, seed=seed, threads=threads)
+                          alpha=alpha, seed=seed, threads=threads, kernel=kernel)
             sst = sub.new_state([v0s[f]])
             o2 = R.initial(v0s[f])
             ties = 0
@@ -63,17 +64,20 @@ def _trajectory(hip, tables, ns, W, b, B, S, prec, seed, alpha=1e-3, temps=None,
 # --------------------------------------------------------------------------
 # Plain method, smallest: N = 256, 1 chain, FP64, seed 0 -- 500-sweep trajectory
 # --------------------------------------------------------------------------
-def test_plain_n256_b1_fp64_trajectory(hip):
+@pytest.mark.parametrize("kernel", ["push", "pull"])
+def test_plain_n256_b1_fp64_trajectory(hip, kernel):
     w = wl.config_workload("plain_n256_b1")
-    _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 1, 500, "f64", w.seed, label="n256 fp64")
+    _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 1, 500, "f64", w.seed, kernel=kernel,
+                label="n256 fp64")
 
 
-def test_plain_n256_b1_fp32_teacher_forced(hip):
+@pytest.mark.parametrize("kernel", ["push", "pull"])
+def test_plain_n256_b1_fp32_teacher_forced(hip, kernel):
     from paper_2311_02101_amd import hp
     w = wl.config_workload("plain_n256_b1")
-    say("[n256 fp32] teacher forced 40 sweeps")
+    say(f"[n256 fp32 {kernel}] teacher forced 40 sweeps")
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=1, temps=w.temps, precision="f32",
-                   seed=w.seed)
+                   seed=w.seed, kernel=kernel)
     st = plan.new_state(w.v0)
     op = R.plan(w.tables[0], 256, w.W, w.b)
     ost = R.initial(w.v0[0])
@@ -84,10 +88,32 @@ def test_plain_n256_b1_fp32_teacher_forced(hip):
 # --------------------------------------------------------------------------
 # Plain method, medium: N = 4096, 64 chains, seed 1 (the benchmark's launch)
 # --------------------------------------------------------------------------
-def test_plain_n4096_b64_fp64_sampled_chains(hip):
+@pytest.mark.parametrize("kernel", ["push", "pull"])
+def test_plain_n4096_b64_fp64_sampled_chains(hip, kernel):
     w = wl.config_workload("plain_n4096_b64")
     _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 64, 40, "f64", w.seed,
-                chains=[0, 1, 31, 32, 62, 63], label="n4096 fp64")
+                chains=[0, 1, 31, 32, 62, 63], kernel=kernel, label="n4096 fp64")
+
+
+def test_push_and_pull_kernels_agree(hip):
+    """The two scatter-add variants differ only in the last bits of x, so
+    their trajectories coincide except at (astronomically rare) ties."""
+    from paper_2311_02101_amd import hp
+    w = wl.config_workload("plain_n4096_b64")
+    out = []
+    for kernel in ("push", "pull"):
+        say(f"[push/pull] {kernel}: 64 chains x 30 sweeps")
+        plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps,
+                       precision="f64", seed=w.seed, kernel=kernel)
+        st = plan.new_state(w.v0)
+        plan.run(st, 30)
+        _sync()
+        out.append(st.formula(0))
+    for a, c in zip(out[0], out[1]):
+        if a.dtype.kind == "f":
+            assert np.max(np.abs(a - c) / c) < 1e-12
+        else:
+            assert np.array_equal(a, c)
 
 
 def test_plain_n4096_b64_fp32_teacher_forced_all_chains(hip):
@@ -147,22 +173,25 @@ def test_uneven_batch_fp32_sampled_formulas(hip):
 # --------------------------------------------------------------------------
 # Edge cases
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("threads", [64, 256, 1024])
-def test_launch_shapes_agree(hip, threads):
-    """Register-resident (1, 4 groups/thread) and global-memory EMA paths."""
+@pytest.mark.parametrize("kernel", ["push", "pull"])
+@pytest.mark.parametrize("threads", [64, 512, 1024])
+def test_launch_shapes_agree(hip, threads, kernel):
+    """Register-resident (1 or 2 groups/thread) and global-memory EMA paths."""
     n = 4096
     T = wl.random_formula(n, 21)
     W, b = wl.gaussian_rbm(2, 7, 8, 21)
-    _trajectory(hip, [T], [n], W, b, 3, 8, "f64", 21, threads=threads, label=f"threads={threads}")
+    _trajectory(hip, [T], [n], W, b, 3, 8, "f64", 21, threads=threads, kernel=kernel,
+                label=f"threads={threads}")
 
 
-def test_tiny_and_ragged_formulas(hip):
+@pytest.mark.parametrize("kernel", ["push", "pull"])
+def test_tiny_and_ragged_formulas(hip, kernel):
     clauses = [[[1]], [[1, -2], [2]], [[3, -1, 2], [-3]], [[-4, 1], [2, 3, 4], [-1, -2, -3]],
                [[5, -1, 2], [-3, 4], [1], [-5, 2, 3]]]
     ns = [1, 2, 3, 4, 5]
     tables = [wl.pad_clauses(cl, 3) for cl in clauses]
     W, b = wl.gaussian_rbm(1, 3, 3, 4)
-    _trajectory(hip, tables, ns, W, b, 5, 30, "f64", 4, label="tiny K=3 L=3")
+    _trajectory(hip, tables, ns, W, b, 5, 30, "f64", 4, kernel=kernel, label="tiny K=3 L=3")
 
 
 def test_zero_padded_literals_are_normalised(hip):
