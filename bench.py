@@ -25,13 +25,14 @@ if ROOT not in sys.path:
 # ---------------------------------------------------------------------------
 # ALU cost model of one chain-sweep (K = 7, L = 8, C = 6N):
 #   Philox4x32-10 calls: C * ceil(L/4) hidden + ceil(N/4) visible
-#   one call = 10 rounds x (2 v_mad_u64_u32 + 4 v_xor_b32) = 60 VALU
-#            instructions, each one issue slot per lane (a Philox-only loop
-#            measures 55 lane-slots per call on MI355X at the rated clock)
+#   one call = 10 rounds x (2 v_mad_u64_u32 + 2 three-input XORs, gfx950's
+#            v_bitop3_b32) = 40 VALU instructions, each one issue slot per
+#            lane (a Philox-only loop with 2-input XORs measures 55 lane-slots
+#            per call for its ~58 instructions at the rated clock)
 #   each Bernoulli draw adds a shift and an unsigned compare (2 slots)
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-slots/s.
 # ---------------------------------------------------------------------------
-PHILOX_SLOTS = 60
+PHILOX_SLOTS = 40
 DRAW_SLOTS = 2
 PEAK_SLOTS = 256 * 64 * 2.4e9
 
@@ -52,6 +53,7 @@ def main(argv=None):
     ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "push", "pull"])
+    ap.add_argument("--split", type=int, default=0, help="workgroups per chain (0 = automatic)")
     ap.add_argument("--cpu-sweeps", type=int, default=10,
                     help="sweeps of the oracle sample (all chains); 0 skips the CPU leg")
     args = ap.parse_args(argv)
@@ -73,7 +75,7 @@ def main(argv=None):
     L = w.W.shape[2]
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=B, temps=w.temps,
                    precision=args.precision, alpha=w.alpha, seed=w.seed, threads=args.threads,
-                   kernel=args.kernel)
+                   kernel=args.kernel, split=args.split)
     st = plan.new_state(w.v0, device=dev)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -90,6 +92,7 @@ def main(argv=None):
         e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    plan.check()
     launch_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
 
@@ -107,6 +110,7 @@ def main(argv=None):
         "config": {"workload": args.workload, "n_vars": N, "clauses": C, "K": 7, "L": L,
                    "chains": B, "sweeps_per_step": args.sweeps, "temperatures": list(wl.FSTAR_PAIR),
                    "threads": plan_threads(args.threads), "kernel": args.kernel,
+                   "launch": plan.info(),
                    "parallelism": "single GPU"},
         "chain_sweeps_per_s": B * args.sweeps * instances / wall,
         "draws_per_s": draws * B * args.sweeps * instances / wall,

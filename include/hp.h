@@ -81,7 +81,9 @@ typedef struct {
     double alpha;                   /* variance moving-average rate, in [0, 1]         */
     uint64_t seed;                  /* Philox key source                               */
     int32_t threads;                /* workgroup size override (0 = automatic)         */
-    int32_t split;                  /* workgroups per chain override (0 = automatic)   */
+    int32_t split;                  /* workgroups per chain of the push kernel: 0 =
+                                       automatic (fill the device), 1 = one, or a power
+                                       of two up to 16 (all must be co-resident)       */
     int32_t kernel;                 /* hp_kernel: sweep kernel variant                 */
 } hp_opts;
 
@@ -136,6 +138,26 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
  * and best; n_sweeps = 0 performs only that count-and-track step.  *t is
  * advanced by n_sweeps.  HP_EINVAL if the state does not match the plan. */
 hp_status hp_run(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
+
+/* How a plan runs (for reports and tuning). */
+typedef struct {
+    int32_t threads;                /* workgroup size                                 */
+    int32_t split;                  /* workgroups per chain of the push launch        */
+    int32_t push_items;             /* (formula, chain) items on the push kernel      */
+    int32_t pull_items;             /* (formula, chain) items on the pull kernel      */
+    int32_t fx_shift;               /* S: push accumulators count units of 2^-S       */
+    int32_t reserved;
+    int64_t lds_push, lds_pull;     /* dynamic LDS bytes per workgroup of each launch */
+} hp_plan_info;
+
+/* Fill *out with the plan's launch configuration.  HP_EINVAL on NULL. */
+hp_status hp_plan_query(hp_plan_t plan, hp_plan_info *out);
+
+/* Wait for the plan's device work and report device-side failures: returns
+ * HP_EDEVICE if a cross-workgroup barrier of a split launch (several
+ * workgroups per chain, hp_opts.split) gave up waiting, in which case the
+ * state written by the affected runs is void; HP_OK otherwise. */
+hp_status hp_check(hp_plan_t plan);
 
 /* Release a plan's device memory (synchronises the device first).  NULL is
  * accepted. */

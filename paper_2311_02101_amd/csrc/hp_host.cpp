@@ -50,8 +50,15 @@ void release(Plan *p) {
     (void)hipFree(p->d_occ);
     (void)hipFree(p->d_rec);
     (void)hipFree(p->d_orig);
+    (void)hipFree(p->d_negcnt);
+    (void)hipFree(p->d_tabflag);
     (void)hipFree(p->tab.gfx);
     (void)hipFree(p->tab.gpad);
+    (void)hipFree(p->d_xpart);
+    (void)hipFree(p->d_vbuf);
+    (void)hipFree(p->d_cnt);
+    (void)hipFree(p->d_bar);
+    (void)hipFree(p->d_err);
     (void)hipFree(p->d_temp);
     (void)hipFree(p->d_W);
     (void)hipFree(p->d_b);
@@ -110,6 +117,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         return fail(HP_EINVAL, "threads must be 0 or a multiple of 64 in [64, 1024]");
     if (opts->kernel < HP_KERNEL_AUTO || opts->kernel > HP_KERNEL_PUSH)
         return fail(HP_EINVAL, "unknown kernel variant");
+    if (opts->split < 0 || opts->split > kMaxSplit || (opts->split & (opts->split - 1)))
+        return fail(HP_EINVAL, "split must be 0 (automatic) or a power of two up to 16");
     for (int i = 0; i < T * K * L; ++i)
         if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
     for (int i = 0; i < T * L; ++i)
@@ -188,6 +197,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     std::vector<uint4> rec(NC);
     std::vector<uint32_t> orig(NC);
     std::vector<uint32_t> push_slots(NV, 0);
+    std::vector<int32_t> negcnt(NV, 0);
     for (int f = 0; f < F; ++f) {
         const int64_t c0 = cnf->clause_offset[f], c1 = cnf->clause_offset[f + 1];
         std::vector<std::pair<int, int64_t>> key;
@@ -196,7 +206,11 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
             int len = K;
             while (len > 1 && lits[(size_t)(len - 1) * NC + c] == lits[c]) --len;
             key.push_back({len, c});
-            for (int k = 0; k < len; ++k) push_slots[cnf->var_offset[f] + (lits[(size_t)k * NC + c] & 0x7fff)]++;
+            for (int k = 0; k < len; ++k) {
+                const uint16_t e = lits[(size_t)k * NC + c];
+                push_slots[cnf->var_offset[f] + (e & 0x7fff)]++;
+                if (e >> 15) negcnt[cnf->var_offset[f] + (e & 0x7fff)]++;
+            }
         }
         std::stable_sort(key.begin(), key.end(),
                          [](const std::pair<int, int64_t> &a, const std::pair<int, int64_t> &b) {
@@ -205,8 +219,11 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         for (int64_t j = 0; j < c1 - c0; ++j) {
             const int len = key[j].first;
             const int64_t c = key[j].second;
-            uint16_t sl[8] = {0, 0, 0, 0, 0, 0, 0, (uint16_t)len};
+            uint16_t sl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            uint32_t negm = 0;
             for (int k = 0; k < K; ++k) sl[k] = lits[(size_t)k * NC + c];
+            for (int k = 0; k < len; ++k) negm |= (uint32_t)(sl[k] >> 15) << k;
+            sl[7] = (uint16_t)(len | (negm << 3));
             rec[c0 + j] = make_uint4(sl[0] | ((uint32_t)sl[1] << 16), sl[2] | ((uint32_t)sl[3] << 16),
                                      sl[4] | ((uint32_t)sl[5] << 16), sl[6] | ((uint32_t)sl[7] << 16));
             orig[c0 + j] = (uint32_t)(c - c0);
@@ -305,6 +322,37 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     work.insert(work.end(), work_pull.begin(), work_pull.end());
     p->n_work = (int32_t)work.size();
 
+    // --- split: G co-resident workgroups per chain for the push items ---
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+    int min_c = INT32_MAX;
+    for (const WorkItem &it : work_push) min_c = std::min(min_c, fd[it.f].c);
+    int G = 1;
+    if (p->n_push > 0 && opts->split != 1) {
+        const int occ = split_occupancy(*p);
+        const int64_t capacity = (int64_t)cus * occ;
+        if (opts->split >= 2) {
+            G = opts->split;
+            if ((int64_t)p->n_push * G > capacity) {
+                release(p);
+                return fail(HP_EUNSUPPORTED, "split " + std::to_string(G) + ": " +
+                                                 std::to_string((int64_t)p->n_push * G) +
+                                                 " workgroups cannot all be resident (capacity " +
+                                                 std::to_string(capacity) + ")");
+            }
+        } else {
+            // largest power of two that keeps every workgroup resident and
+            // leaves each member at least 1024 clauses
+            while (G * 2 <= kMaxSplit && (int64_t)p->n_push * G * 2 <= capacity &&
+                   min_c / (G * 2) >= 1024)
+                G *= 2;
+        }
+    }
+    p->split = G;
+    p->nstride = ((int64_t)pn + 15) / 16 * 16;
+    p->xcd_map = (p->n_push % 8 == 0) ? 1 : 0;
+
     // --- device upload ---
     hipStream_t s = (hipStream_t)stream;
     std::vector<double> Wv(rbm->W, rbm->W + (size_t)T * K * L), bv(rbm->b, rbm->b + (size_t)T * L);
@@ -324,6 +372,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(upload(&p->d_occ, occ, s), "upload occurrences");
     HP_TRY(upload(&p->d_rec, rec, s), "upload clause records");
     HP_TRY(upload(&p->d_orig, orig, s), "upload clause order");
+    HP_TRY(upload(&p->d_negcnt, negcnt, s), "upload negation counts");
     HP_TRY(upload(&p->d_temp, temp, s), "upload temperatures");
     HP_TRY(upload(&p->d_W, Wv, s), "upload W_c");
     HP_TRY(upload(&p->d_b, bv, s), "upload b_c");
@@ -332,10 +381,27 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
     HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kMaxL * sizeof(int64_t)), "alloc gfx");
     HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kMaxL * kHidMasks * sizeof(int64_t)), "alloc gpad");
+    HP_TRY(hipMalloc((void **)&p->d_err, sizeof(int32_t)), "alloc error flag");
+    HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_err), 1, s), "clear error flag");
+    HP_TRY(hipMalloc((void **)&p->d_tabflag, sizeof(int32_t)), "alloc table flag");
+    HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_tabflag), 1, s), "clear table flag");
+    if (p->split > 1) {
+        const size_t items = (size_t)p->n_push;
+        HP_TRY(hipMalloc((void **)&p->d_xpart, items * p->split * p->nstride * sizeof(int64_t)), "alloc xpart");
+        HP_TRY(hipMalloc((void **)&p->d_vbuf, items * p->nstride), "alloc vbuf");
+        HP_TRY(hipMalloc((void **)&p->d_cnt, items * kMaxSplit * sizeof(int32_t)), "alloc counts");
+        HP_TRY(hipMalloc((void **)&p->d_bar, items * 32 * sizeof(uint32_t)), "alloc barriers");
+    }
     HP_TRY(launch_tables(*p, s), "table kernel");
     // host staging vectors go out of scope below: wait for the copies
     HP_TRY(hipStreamSynchronize(s), "plan upload");
+    int32_t tabflag = 0;
+    HP_TRY(hipMemcpy(&tabflag, p->d_tabflag, sizeof(tabflag), hipMemcpyDeviceToHost), "table flag");
 #undef HP_TRY
+    if (tabflag) {
+        release(p);
+        return fail(HP_EUNSUPPORTED, "a hidden-unit probability underflows to 0 (logit below -709)");
+    }
     *out = reinterpret_cast<hp_plan_t>(p);
     return HP_OK;
 }
@@ -356,6 +422,37 @@ hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *str
     if (dev != p->device) return fail(HP_EINVAL, "plan was built on another device");
     e = launch_sweep(*p, *st, n_sweeps, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    return HP_OK;
+}
+
+hp_status hp_plan_query(hp_plan_t plan, hp_plan_info *out) {
+    g_last_error.clear();
+    const Plan *p = reinterpret_cast<const Plan *>(plan);
+    if (!p || !out) return fail(HP_EINVAL, "null argument");
+    out->threads = p->threads;
+    out->split = p->split;
+    out->push_items = p->n_push;
+    out->pull_items = p->n_work - p->n_push;
+    out->fx_shift = p->fx_shift;
+    out->reserved = 0;
+    out->lds_push = (int64_t)p->lds_push;
+    out->lds_pull = (int64_t)p->lds_pull;
+    return HP_OK;
+}
+
+hp_status hp_check(hp_plan_t plan) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p) return fail(HP_EINVAL, "null plan");
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    hipError_t e = hipDeviceSynchronize();
+    int32_t flag = 0;
+    if (e == hipSuccess) e = hipMemcpy(&flag, p->d_err, sizeof(flag), hipMemcpyDeviceToHost);
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hp_check");
+    if (flag) return fail(HP_EDEVICE, "a cross-workgroup barrier timed out; results of the affected runs are void");
     return HP_OK;
 }
 

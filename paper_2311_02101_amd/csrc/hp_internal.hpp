@@ -53,9 +53,12 @@ struct DeviceTables {
 
 // Clause record of the push kernel: 8 x 16-bit slots in a uint4.  Slots
 // 0..6 hold literal k as (0-based variable index) | (negated << 15); slot 7
-// holds the clause length len (positions >= len repeat literal 0).  Records
-// of a formula are sorted by len (stable); orig[] keeps the clause's index
-// in the input, which addresses its random numbers.
+// holds len | (negation bits of slots 0..len-1) << 3, where len is the
+// clause length (positions >= len repeat literal 0).  Records of a formula
+// are sorted by len (stable); orig[] keeps the clause's index in the input,
+// which addresses its random numbers.
+//
+// thr[tau][m][l] holds 256 * ceil(2^24 p) - 1 (see the table kernel).
 
 template <typename Real>
 struct SweepParams {
@@ -66,6 +69,7 @@ struct SweepParams {
     const uint32_t *occ;         // pull: (c_local << 4) | (negated << 3) | k, (c, k) ascending
     const uint4 *rec;            // push: clause records [ctot]
     const uint32_t *orig;        // push: input clause index [ctot]
+    const int32_t *negcnt;       // push: negated slots per variable [sum N]
     const uint32_t *thr;         // [T][128][8]
     const Real *G;               // [T][256][8]
     const int64_t *gfx;          // [T][256][8]
@@ -88,6 +92,22 @@ struct SweepParams {
     int32_t lds_x_off;           // push: int64 accumulators
 };
 
+// Split launch: the G workgroups of one chain exchange, every sweep, their
+// partial fixed-point logits (xpart) and the owners' new values (vbuf).
+constexpr int kMaxSplit = 16;
+
+struct SplitParams {
+    int64_t *xpart;              // [items][G][nstride]
+    uint8_t *vbuf;               // [items][nstride]
+    int32_t *cnt;                // [items][kMaxSplit] partial clause counts
+    uint32_t *bar;               // [items][32] barrier counters (one 128-byte line each)
+    int32_t *err;                // [1] barrier timeout flag
+    int64_t nstride;
+    int32_t G;
+    int32_t xcd_map;             // members of an item on the same XCD
+    int32_t n_xcd;
+};
+
 enum class Variant { kPull = 0, kPush = 1 };
 
 struct Plan {
@@ -107,6 +127,9 @@ struct Plan {
     size_t lds_push = 0, lds_pull = 0;
     int32_t push_v_off = 0, push_x_off = 0;
     int32_t pull_v_off = 0, pull_hm_off = 0;
+    int32_t split = 1;           // G workgroups per chain for the push items
+    int32_t xcd_map = 0;
+    int64_t nstride = 0;
     int device = 0;
     // device memory
     FormulaDev *d_fd = nullptr;
@@ -116,16 +139,28 @@ struct Plan {
     uint32_t *d_occ = nullptr;
     uint4 *d_rec = nullptr;
     uint32_t *d_orig = nullptr;
+    int32_t *d_negcnt = nullptr;
+    int32_t *d_tabflag = nullptr;
     int32_t *d_temp = nullptr;
     double *d_W = nullptr;
     double *d_b = nullptr;
     DeviceTables tab;
     int32_t n_work = 0;
+    int64_t *d_xpart = nullptr;
+    uint8_t *d_vbuf = nullptr;
+    int32_t *d_cnt = nullptr;
+    uint32_t *d_bar = nullptr;
+    int32_t *d_err = nullptr;
 };
 
 // kernels / launchers (hp_kernels.hip)
 hipError_t launch_tables(const Plan &p, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s);
+
+hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t s);
+
+// resident workgroups per CU of the split kernel for this plan's launch shape
+int split_occupancy(const Plan &p);
 
 // LDS bytes of the two kernel variants for the largest formula
 size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);

@@ -35,6 +35,7 @@
 #include "hp_internal.hpp"
 #include "philox.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace hp {
@@ -58,7 +59,7 @@ __device__ int64_t g_fixed(const double *__restrict__ Wt, int K, int L, int n, i
 __global__ void tables_kernel(const double *__restrict__ W, const double *__restrict__ b, int K, int L,
                               int T, int S, uint32_t *__restrict__ thr, double *__restrict__ g64,
                               float *__restrict__ g32, int64_t *__restrict__ gfx,
-                              int64_t *__restrict__ gpad) {
+                              int64_t *__restrict__ gpad, int32_t *__restrict__ flag) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int n_thr = T * kPatterns * kMaxL;
     const int n_g = T * kHidMasks * kMaxL;
@@ -73,7 +74,11 @@ __global__ void tables_kernel(const double *__restrict__ W, const double *__rest
             for (int k = 0; k < K; ++k)
                 if ((m >> k) & 1) z += Wt[k * L + l];
             const double p = 1.0 / (1.0 + exp(-z));
-            out = (uint32_t)ceil(p * 16777216.0);   // exact scaling by 2^24
+            // c = ceil(2^24 p) (exact scaling); U < p  <=>  (word >> 8) < c
+            // <=>  word <= 256 c - 1, which fits 32 bits for 1 <= c <= 2^24
+            const uint32_t c = (uint32_t)ceil(p * 16777216.0);
+            if (c == 0u) *flag = 1;               // p underflowed to 0: not representable
+            out = c * 256u - 1u;
         }
         thr[tid] = out;
     }
@@ -101,7 +106,7 @@ __global__ void tables_kernel(const double *__restrict__ W, const double *__rest
 hipError_t launch_tables(const Plan &p, hipStream_t s) {
     const int n = p.T * kHidMasks * kMaxL;   // >= the threshold table size
     tables_kernel<<<(n + 255) / 256, 256, 0, s>>>(p.d_W, p.d_b, p.K, p.L, p.T, p.fx_shift, p.tab.thr,
-                                                  p.tab.g64, p.tab.g32, p.tab.gfx, p.tab.gpad);
+                                                  p.tab.g64, p.tab.g32, p.tab.gfx, p.tab.gpad, p.d_tabflag);
     return hipGetLastError();
 }
 
@@ -149,6 +154,31 @@ size_t lds_bytes_push(int max_n, int32_t *v_off, int32_t *x_off) {
     return off;
 }
 
+// Hidden draw of one clause: L Bernoulli bits against the pre-shifted
+// thresholds row[l] = 256 ceil(2^24 p_l) - 1 of its literal pattern, bit l
+// set iff word_l <= row[l] (i.e. U < p_l).  Units of the first Philox block
+// go to bits 0..3, of the second block (L > 4) to bits 4..7; bits >= L are
+// left to the caller to mask.
+__device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t tlo, uint32_t thi,
+                                                uint32_t chain, uint32_t blk, Key2 key, uint32_t nbh) {
+    const uint4 ta = *reinterpret_cast<const uint4 *>(row);
+    const uint4 ra = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | blk, thi), key);
+    uint32_t n = (uint32_t)(ra.w <= ta.w);
+    n = n + n + (uint32_t)(ra.z <= ta.z);
+    n = n + n + (uint32_t)(ra.y <= ta.y);
+    n = n + n + (uint32_t)(ra.x <= ta.x);
+    if (nbh > 1) {
+        const uint4 tb = *reinterpret_cast<const uint4 *>(row + 4);
+        const uint4 rb = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | (blk + 1u), thi), key);
+        uint32_t h = (uint32_t)(rb.w <= tb.w);
+        h = h + h + (uint32_t)(rb.z <= tb.z);
+        h = h + h + (uint32_t)(rb.y <= tb.y);
+        h = h + h + (uint32_t)(rb.x <= tb.x);
+        n |= h << 4;
+    }
+    return n;
+}
+
 // VPT > 0: each thread owns VPT groups of 4 consecutive variables and keeps
 // their variance EMA in registers.  VPT == 0: any number of groups, EMA read
 // and written in global memory every sweep.
@@ -174,6 +204,7 @@ __global__ __launch_bounds__(1024) void sweep_pull_kernel(SweepParams<Real> P) {
     const bool sample = P.n_sweeps > 0;
     const int64_t S = sample ? P.n_sweeps : 1;
     const uint32_t nbh = (uint32_t)(P.L + 3) >> 2;
+    const uint32_t lmask = (1u << P.L) - 1u;
     const int K = P.K;
     const int64_t ctot = P.ctot;
     const Real alpha = P.alpha;
@@ -213,16 +244,8 @@ __global__ __launch_bounds__(1024) void sweep_pull_kernel(SweepParams<Real> P) {
             }
             cnt += (m != 0u);
             if (sample) {
-                const uint4 t0v = *reinterpret_cast<const uint4 *>(s_thr + m * kMaxL);
-                uint4 r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseHidden | ((uint32_t)c * nbh), thi), key);
-                uint32_t n = (uint32_t)((r.x >> 8) < t0v.x) | ((uint32_t)((r.y >> 8) < t0v.y) << 1) |
-                             ((uint32_t)((r.z >> 8) < t0v.z) << 2) | ((uint32_t)((r.w >> 8) < t0v.w) << 3);
-                if (nbh > 1) {
-                    const uint4 t1v = *reinterpret_cast<const uint4 *>(s_thr + m * kMaxL + 4);
-                    r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseHidden | ((uint32_t)c * nbh + 1u), thi), key);
-                    n |= ((uint32_t)((r.x >> 8) < t1v.x) << 4) | ((uint32_t)((r.y >> 8) < t1v.y) << 5) |
-                         ((uint32_t)((r.z >> 8) < t1v.z) << 6) | ((uint32_t)((r.w >> 8) < t1v.w) << 7);
-                }
+                uint32_t n = hidden_mask(s_thr + m * kMaxL, tlo, thi, (uint32_t)w.b, (uint32_t)c * nbh, key,
+                                         nbh) & lmask;
                 s_hm[c] = (uint8_t)n;
             }
         }
@@ -291,20 +314,119 @@ __device__ __forceinline__ uint32_t lit_of(const uint8_t *s_v, uint32_t e) {
     return (uint32_t)s_v[e & 0x7fffu] ^ (e >> 15);
 }
 
+// Add pol * g to the accumulator of slot e's variable.  A negated slot adds
+// ~g = -g - 1; the missing +1 of every negated slot of a variable is a
+// constant of the formula (negcnt) that seeds the accumulator.
 __device__ __forceinline__ void push_add(int64_t *s_x, uint32_t e, int64_t g) {
-    atomicAdd(reinterpret_cast<unsigned long long *>(&s_x[e & 0x7fffu]),
-              (unsigned long long)((e >> 15) ? -g : g));
+    const uint64_t sm = (uint64_t)(int64_t)((int32_t)(e << 16) >> 31);   // 0 or all ones
+    atomicAdd(reinterpret_cast<unsigned long long *>(&s_x[e & 0x7fffu]), (unsigned long long)g ^ sm);
+}
+
+// LDS views of the push layout
+struct PushLds {
+    uint32_t *thr;
+    int64_t *gfx;
+    int64_t *gpad;
+    int *cnt;
+    int64_t *x;
+    uint8_t *v;
+};
+
+__device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off, int v_off) {
+    return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kPushGfxOff),
+                   reinterpret_cast<int64_t *>(lds + kPushGpadOff), reinterpret_cast<int *>(lds + kPushCntOff),
+                   reinterpret_cast<int64_t *>(lds + x_off), lds + v_off};
+}
+
+__device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_t *thr, const int64_t *gfx,
+                                                 const int64_t *gpad, int tau, int tid, int NT) {
+    for (int i = tid; i < kPatterns * kMaxL; i += NT) L.thr[i] = thr[tau * kPatterns * kMaxL + i];
+    for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
+        L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
+        L.gpad[i] = gpad[tau * kHidMasks * kMaxL + i];
+    }
+}
+
+// Clause phase over the clause records c = c_first + c_step * j, c < c_end,
+// j strided over the workgroup:
+// gather, literal-truth pattern, count; when sampling, the hidden draw and the
+// scatter of the clause's contributions into the LDS accumulators.  Returns
+// this thread's number of satisfied clauses.
+template <bool kSample>
+__device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
+                                            const uint32_t *__restrict__ orig, int c_first, int c_step,
+                                            int c_end, int tid, int NT, uint32_t tlo, uint32_t thi, uint32_t chain,
+                                            Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
+    int cnt = 0;
+    uint4 r_next = make_uint4(0, 0, 0, 0);
+    uint32_t o_next = 0;
+    const int c_inc = c_step * NT;
+    if (c_first + c_step * tid < c_end) {
+        r_next = rec[c_first + c_step * tid];
+        o_next = orig[c_first + c_step * tid];
+    }
+    for (int c = c_first + c_step * tid; c < c_end; c += c_inc) {
+        const uint4 r = r_next;
+        const uint32_t oc = o_next;
+        if (c + c_inc < c_end) {       // prefetch the next record
+            r_next = rec[c + c_inc];
+            o_next = orig[c + c_inc];
+        }
+        const uint32_t len = (r.w >> 16) & 7u;
+        const uint32_t negm = r.w >> 19;          // negation bits of slots 0..len-1
+        const uint32_t e0 = r.x & 0xffffu, e1 = r.x >> 16, e2 = r.y & 0xffffu, e3 = r.y >> 16;
+        const uint32_t e4 = r.z & 0xffffu, e5 = r.z >> 16, e6 = r.w & 0xffffu;
+        // gather the values of the clause's variables, then apply the polarities
+        uint32_t m = L.v[e0 & 0x7fffu];
+        if (len > 1) m |= (uint32_t)L.v[e1 & 0x7fffu] << 1;
+        if (len > 2) m |= (uint32_t)L.v[e2 & 0x7fffu] << 2;
+        if (len > 3) m |= (uint32_t)L.v[e3 & 0x7fffu] << 3;
+        if (len > 4) m |= (uint32_t)L.v[e4 & 0x7fffu] << 4;
+        if (len > 5) m |= (uint32_t)L.v[e5 & 0x7fffu] << 5;
+        if (len > 6) m |= (uint32_t)L.v[e6 & 0x7fffu] << 6;
+        m ^= negm;
+        m |= (m & 1u) ? (full & ~((1u << len) - 1u)) : 0u;   // padding copies of literal 0
+        cnt += (m != 0u);
+        if (kSample) {
+            const uint32_t n = hidden_mask(L.thr + m * kMaxL, tlo, thi, chain, oc * nbh, key, nbh) & lmask;
+            push_add(L.x, e0, L.gpad[len * kHidMasks + n]);
+            const int64_t *gr = L.gfx + n * kMaxL;
+            if (len > 1) push_add(L.x, e1, gr[1]);
+            if (len > 2) push_add(L.x, e2, gr[2]);
+            if (len > 3) push_add(L.x, e3, gr[3]);
+            if (len > 4) push_add(L.x, e4, gr[4]);
+            if (len > 5) push_add(L.x, e5, gr[5]);
+            if (len > 6) push_add(L.x, e6, gr[6]);
+        }
+    }
+    return cnt;
+}
+
+// Visible update of one variable from its fixed-point logit: sigmoid, EMA,
+// Bernoulli draw U < rho with U = (word >> 8) 2^-24.
+template <typename Real>
+__device__ __forceinline__ uint8_t visible_update(int64_t xi, double fx_scale, Real &nu, Real alpha,
+                                                  uint32_t word) {
+    const Real x = (Real)((double)xi * fx_scale);
+    const Real rho = sigmoid(x);
+    nu = ema(nu, rho, alpha);
+    return (Real(word >> 8) * Real(1.0 / 16777216.0)) < rho ? 1 : 0;
+}
+
+// workgroup total of a per-thread count (uses L.cnt; ends with a barrier)
+__device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, int NT) {
+    cnt = wave_sum(cnt);
+    if ((tid & (kWave - 1)) == 0) L.cnt[tid / kWave] = cnt;
+    __syncthreads();
+    int total = 0;
+    for (int wv = 0; wv < NT / kWave; ++wv) total += L.cnt[wv];
+    return total;
 }
 
 template <typename Real, int VPT>
 __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
     extern __shared__ __align__(16) unsigned char lds[];
-    uint32_t *s_thr = reinterpret_cast<uint32_t *>(lds);
-    int64_t *s_gfx = reinterpret_cast<int64_t *>(lds + kPushGfxOff);
-    int64_t *s_gpad = reinterpret_cast<int64_t *>(lds + kPushGpadOff);
-    int *s_cnt = reinterpret_cast<int *>(lds + kPushCntOff);
-    int64_t *s_x = reinterpret_cast<int64_t *>(lds + P.lds_x_off);
-    uint8_t *s_v = lds + P.lds_v_off;
+    const PushLds L = push_lds(lds, P.lds_x_off, P.lds_v_off);
 
     const WorkItem w = P.work[blockIdx.x];
     const FormulaDev fd = P.fd[w.f];
@@ -319,21 +441,19 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
     const int64_t S = sample ? P.n_sweeps : 1;
     const uint32_t nbh = (uint32_t)(P.L + 3) >> 2;
     const uint32_t full = (1u << P.K) - 1u;
+    const uint32_t lmask = (1u << P.L) - 1u;
     const Real alpha = P.alpha;
     const double fx_scale = P.fx_scale;
-    const Real two_m24 = Real(1.0 / 16777216.0);
+    const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
 
-    for (int i = tid; i < kPatterns * kMaxL; i += NT) s_thr[i] = P.thr[tau * kPatterns * kMaxL + i];
-    for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
-        s_gfx[i] = P.gfx[tau * kHidMasks * kMaxL + i];
-        s_gpad[i] = P.gpad[tau * kHidMasks * kMaxL + i];
-    }
+    load_push_tables(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
-        s_v[i] = P.v[sbase + i];
-        s_x[i] = 0;
+        L.v[i] = P.v[sbase + i];
+        L.x[i] = negcnt[i];
     }
     constexpr int VR = VPT > 0 ? VPT : 1;
     Real nu[VR][4];
+    int32_t ncr[VR][4];
     if (VPT > 0) {
 #pragma unroll
         for (int j = 0; j < VR; ++j)
@@ -341,6 +461,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
             for (int q = 0; q < 4; ++q) {
                 const int i = (tid + j * NT) * 4 + q;
                 nu[j][q] = i < N ? P.nu[sbase + i] : Real(0);
+                ncr[j][q] = i < N ? negcnt[i] : 0;
             }
     }
     int smax = P.s_max[(int64_t)w.f * P.B + w.b];
@@ -350,63 +471,12 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
     for (int64_t s = 0; s < S; ++s) {
         const uint64_t t = (uint64_t)(t0 + s);
         const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-        // ---- clause phase: gather, count, hidden draw, scatter into x ----
-        int cnt = 0;
-        uint4 r_next = make_uint4(0, 0, 0, 0);
-        uint32_t o_next = 0;
-        if (tid < C) {
-            r_next = rec[tid];
-            o_next = orig[tid];
-        }
-        for (int c = tid; c < C; c += NT) {
-            const uint4 r = r_next;
-            const uint32_t oc = o_next;
-            if (c + NT < C) {           // prefetch the next record
-                r_next = rec[c + NT];
-                o_next = orig[c + NT];
-            }
-            const uint32_t len = r.w >> 16;
-            const uint32_t e0 = r.x & 0xffffu, e1 = r.x >> 16, e2 = r.y & 0xffffu, e3 = r.y >> 16;
-            const uint32_t e4 = r.z & 0xffffu, e5 = r.z >> 16, e6 = r.w & 0xffffu;
-            const uint32_t l0 = lit_of(s_v, e0);
-            uint32_t m = l0;
-            if (len > 1) m |= lit_of(s_v, e1) << 1;
-            if (len > 2) m |= lit_of(s_v, e2) << 2;
-            if (len > 3) m |= lit_of(s_v, e3) << 3;
-            if (len > 4) m |= lit_of(s_v, e4) << 4;
-            if (len > 5) m |= lit_of(s_v, e5) << 5;
-            if (len > 6) m |= lit_of(s_v, e6) << 6;
-            m |= l0 ? (full & ~((1u << len) - 1u)) : 0u;   // padding copies of literal 0
-            cnt += (m != 0u);
-            if (sample) {
-                const uint4 ta = *reinterpret_cast<const uint4 *>(s_thr + m * kMaxL);
-                uint4 ra = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseHidden | (oc * nbh), thi), key);
-                uint32_t n = (uint32_t)((ra.x >> 8) < ta.x) | ((uint32_t)((ra.y >> 8) < ta.y) << 1) |
-                             ((uint32_t)((ra.z >> 8) < ta.z) << 2) | ((uint32_t)((ra.w >> 8) < ta.w) << 3);
-                if (nbh > 1) {
-                    const uint4 tb = *reinterpret_cast<const uint4 *>(s_thr + m * kMaxL + 4);
-                    const uint4 rb = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseHidden | (oc * nbh + 1u), thi), key);
-                    n |= ((uint32_t)((rb.x >> 8) < tb.x) << 4) | ((uint32_t)((rb.y >> 8) < tb.y) << 5) |
-                         ((uint32_t)((rb.z >> 8) < tb.z) << 6) | ((uint32_t)((rb.w >> 8) < tb.w) << 7);
-                }
-                push_add(s_x, e0, s_gpad[len * kHidMasks + n]);
-                const int64_t *gr = s_gfx + n * kMaxL;
-                if (len > 1) push_add(s_x, e1, gr[1]);
-                if (len > 2) push_add(s_x, e2, gr[2]);
-                if (len > 3) push_add(s_x, e3, gr[3]);
-                if (len > 4) push_add(s_x, e4, gr[4]);
-                if (len > 5) push_add(s_x, e5, gr[5]);
-                if (len > 6) push_add(s_x, e6, gr[6]);
-            }
-        }
-        cnt = wave_sum(cnt);
-        if ((tid & (kWave - 1)) == 0) s_cnt[tid / kWave] = cnt;
-        __syncthreads();
-        int total = 0;
-        for (int wv = 0; wv < NT / kWave; ++wv) total += s_cnt[wv];
+        const int cnt = sample ? clause_phase<true>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
+                               : clause_phase<false>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
+        const int total = block_total(L, cnt, tid, NT);
         const bool improved = total > smax;
         if (improved) smax = total;
-        // ---- visible phase: sigmoid of the accumulated logit, EMA, draw ----
+        // ---- visible phase ----
         const int groups = (N + 3) >> 2;
         const int jmax = VPT > 0 ? VPT : (groups + NT - 1) / NT;
 #pragma unroll
@@ -421,19 +491,17 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
                 for (int q = 0; q < 4; ++q) {
                     const int i = grp * 4 + q;
                     if (i < N) {
-                        const uint8_t old = s_v[i];
-                        if (improved) P.best[sbase + i] = old;
+                        if (improved) P.best[sbase + i] = L.v[i];
                         if (sample) {
-                            const int64_t xi = s_x[i];
-                            s_x[i] = 0;
-                            const Real x = (Real)((double)xi * fx_scale);
-                            const Real rho = sigmoid(x);
+                            const int64_t xi = L.x[i];
+                            L.x[i] = VPT > 0 ? ncr[j][q] : negcnt[i];
                             if (VPT > 0) {
-                                nu[j][q] = ema(nu[j][q], rho, alpha);
+                                L.v[i] = visible_update(xi, fx_scale, nu[j][q], alpha, rw[q]);
                             } else {
-                                P.nu[sbase + i] = ema(P.nu[sbase + i], rho, alpha);
+                                Real nv = P.nu[sbase + i];
+                                L.v[i] = visible_update(xi, fx_scale, nv, alpha, rw[q]);
+                                P.nu[sbase + i] = nv;
                             }
-                            s_v[i] = (Real(rw[q] >> 8) * two_m24) < rho ? 1 : 0;
                         }
                     }
                 }
@@ -442,7 +510,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
         }
         __syncthreads();
     }
-    for (int i = tid; i < N; i += NT) P.v[sbase + i] = s_v[i];
+    for (int i = tid; i < N; i += NT) P.v[sbase + i] = L.v[i];
     if (VPT > 0) {
 #pragma unroll
         for (int j = 0; j < VR; ++j)
@@ -453,6 +521,209 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
             }
     }
     if (tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;
+}
+
+// --------------------------------------------------------------------------
+// Split kernel: G co-resident workgroups per chain
+// --------------------------------------------------------------------------
+constexpr uint32_t kSpinLimit = 1u << 25;   // ~1 s of s_sleep before giving up
+
+// Exchange between the G workgroups of one chain.  Everything that crosses
+// workgroups (partial logits, partial counts, new values) is written and read
+// with agent-scope atomic stores and loads: those bypass the non-coherent
+// caches, so no cache-wide write-back or invalidation is needed (an
+// agent-scope fence pair costs several microseconds per barrier on MI355X,
+// a barrier without it well under one).
+__device__ __forceinline__ void xstore(int64_t *p, int64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t xload(const int64_t *p) {
+    return __hip_atomic_load(const_cast<int64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t xload(const uint32_t *p) {
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier among the G workgroups of one chain.  Counter `ctr` is zeroed
+// before the launch and incremented once per workgroup per barrier, so the
+// k-th barrier completes when it reaches k*G.  Every thread first waits until
+// its own exchange stores are acknowledged, so they are complete before the
+// workgroup's arrival is counted; the exchange loads that follow the barrier
+// are issued only after the completed count has been observed.  The wait is
+// bounded: on timeout the error flag is raised and the workgroup continues
+// (its results are then void), so no launch can hang.
+__device__ __forceinline__ void group_barrier(uint32_t *ctr, uint32_t target, int32_t *err) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename Real, int VPT>
+__global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, SplitParams Q) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const PushLds L = push_lds(lds, P.lds_x_off, P.lds_v_off);
+
+    // workgroup -> (item, member g); with the XCD map the G members of an
+    // item get workgroup ids congruent modulo the XCD count (same L2)
+    const int G = Q.G;
+    int item, g;
+    if (Q.xcd_map) {
+        const int xcd = blockIdx.x % Q.n_xcd, slot = blockIdx.x / Q.n_xcd;
+        item = (slot / G) * Q.n_xcd + xcd;
+        g = slot % G;
+    } else {
+        item = blockIdx.x / G;
+        g = blockIdx.x % G;
+    }
+    const WorkItem w = P.work[item];
+    const FormulaDev fd = P.fd[w.f];
+    const int N = fd.n, C = fd.c;
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int tau = P.temp_of_chain[w.b];
+    const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
+    const uint4 *__restrict__ rec = P.rec + fd.clause_off;
+    const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
+    const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
+    const bool sample = P.n_sweeps > 0;
+    const int64_t S = sample ? P.n_sweeps : 1;
+    const uint32_t nbh = (uint32_t)(P.L + 3) >> 2;
+    const uint32_t full = (1u << P.K) - 1u;
+    const uint32_t lmask = (1u << P.L) - 1u;
+    const Real alpha = P.alpha;
+    const double fx_scale = P.fx_scale;
+    const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
+    // this member's owned variable groups (of 4)
+    const int groups = (N + 3) >> 2;
+    const int gg = (groups + G - 1) / G;
+    const int q_lo = min(groups, g * gg), q_hi = min(groups, q_lo + gg);
+    // exchange buffers of this item
+    int64_t *xpart = Q.xpart + (size_t)item * G * Q.nstride;
+    uint32_t *vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
+    int32_t *pcnt = Q.cnt + (size_t)item * kMaxSplit;
+    uint32_t *ctr = Q.bar + (size_t)item * 32;
+
+    load_push_tables(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+    for (int i = tid; i < N; i += NT) {
+        L.v[i] = P.v[sbase + i];
+        L.x[i] = 0;
+    }
+    constexpr int VR = VPT > 0 ? VPT : 1;
+    Real nu[VR][4];
+    if (VPT > 0) {
+#pragma unroll
+        for (int j = 0; j < VR; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int grp = q_lo + tid + j * NT;
+                const int i = grp * 4 + q;
+                nu[j][q] = (grp < q_hi && i < N) ? P.nu[sbase + i] : Real(0);
+            }
+    }
+    int smax = P.s_max[(int64_t)w.f * P.B + w.b];
+    const int64_t t0 = *P.t_ptr;
+    uint32_t phase = 0;
+    __syncthreads();
+
+    for (int64_t s = 0; s < S; ++s) {
+        const uint64_t t = (uint64_t)(t0 + s);
+        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+        // member g takes every G-th record of the length-sorted order, so all
+        // members get the same mix of clause lengths
+        const int cnt = sample ? clause_phase<true>(L, rec, orig, g, G, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
+                               : clause_phase<false>(L, rec, orig, g, G, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
+        const int part = block_total(L, cnt, tid, NT);
+        // publish the partial logits of every variable and the partial count
+        if (sample) {
+            for (int i = tid; i < N; i += NT) {
+                xstore(&xpart[(size_t)g * Q.nstride + i], L.x[i]);
+                L.x[i] = 0;
+            }
+        }
+        if (tid == 0) xstore(reinterpret_cast<uint32_t *>(&pcnt[g]), (uint32_t)part);
+        group_barrier(ctr, ++phase * (uint32_t)G, Q.err);
+        int total = 0;
+        for (int k = 0; k < G; ++k) total += (int)xload(reinterpret_cast<const uint32_t *>(&pcnt[k]));
+        const bool improved = total > smax;
+        if (improved) smax = total;
+        // visible phase on the owned groups
+#pragma unroll
+        for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
+          const int jmax = VPT > 0 ? j + 1 : (q_hi - q_lo + NT - 1) / NT;
+          for (int jj = (VPT > 0 ? j : 0); jj < jmax; ++jj) {
+            const int grp = q_lo + tid + jj * NT;
+            if (grp < q_hi) {
+                uint4 r = make_uint4(0, 0, 0, 0);
+                if (sample) r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseVisible | (uint32_t)grp, thi), key);
+                const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+                uint32_t packed = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = grp * 4 + q;
+                    if (i < N) {
+                        if (improved) P.best[sbase + i] = L.v[i];
+                        if (sample) {
+                            int64_t xi = negcnt[i];
+                            for (int k = 0; k < G; ++k) xi += xload(&xpart[(size_t)k * Q.nstride + i]);
+                            uint8_t nvb;
+                            if (VPT > 0) {
+                                nvb = visible_update(xi, fx_scale, nu[j][q], alpha, rw[q]);
+                            } else {
+                                Real nv = P.nu[sbase + i];
+                                nvb = visible_update(xi, fx_scale, nv, alpha, rw[q]);
+                                P.nu[sbase + i] = nv;
+                            }
+                            L.v[i] = nvb;
+                            packed |= (uint32_t)nvb << (8 * q);
+                        }
+                    }
+                }
+                if (sample) xstore(&vbuf[grp], packed);
+            }
+          }
+        }
+        if (sample) {
+            group_barrier(ctr, ++phase * (uint32_t)G, Q.err);
+            for (int q = tid; q < groups; q += NT) {
+                const uint32_t word = xload(&vbuf[q]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (q * 4 + k < N) L.v[q * 4 + k] = (uint8_t)(word >> (8 * k));
+            }
+            __syncthreads();
+        }
+    }
+    // write back the owned part of the state
+    for (int i = q_lo * 4 + tid; i < min(N, q_hi * 4); i += NT) P.v[sbase + i] = L.v[i];
+    if (VPT > 0) {
+#pragma unroll
+        for (int j = 0; j < VR; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int grp = q_lo + tid + j * NT;
+                const int i = grp * 4 + q;
+                if (grp < q_hi && i < N) P.nu[sbase + i] = nu[j][q];
+            }
+    }
+    if (g == 0 && tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 __global__ void advance_t_kernel(int64_t *t, int64_t n) {
@@ -479,6 +750,36 @@ hipError_t launch_variant(bool push, int vpt, int n_items, size_t lds, int threa
     }
 }
 
+hipError_t launch_zero(uint32_t *ptr, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    zero_u32_kernel<<<blocks, 256, 0, s>>>(ptr, n);
+    return hipGetLastError();
+}
+
+int split_occupancy(const Plan &p) {
+    int nb = 0;
+    const void *kern = p.precision == HP_FP64 ? (const void *)sweep_split_kernel<double, 1>
+                                               : (const void *)sweep_split_kernel<float, 1>;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_push) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, p.threads, p.lds_push) != hipSuccess) return 0;
+    return nb;
+}
+
+template <typename Real, int VPT>
+hipError_t launch_split_one(const Plan &p, SweepParams<Real> P, SplitParams Q, hipStream_t s) {
+    auto kern = sweep_split_kernel<Real, VPT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)p.lds_push);
+    if (e != hipSuccess) return e;
+    void *args[] = {(void *)&P, (void *)&Q};
+    // cooperative launch: fails instead of running if the G workgroups of a
+    // chain could not all be resident at once
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(p.n_push * p.split), dim3(p.threads), args,
+                                      (unsigned)p.lds_push, s);
+}
+
 template <typename Real>
 hipError_t launch_sweep_t(const Plan &p, const hp_state &st, int64_t n_sweeps, const Real *G,
                           hipStream_t s) {
@@ -490,6 +791,7 @@ hipError_t launch_sweep_t(const Plan &p, const hp_state &st, int64_t n_sweeps, c
     P.occ = p.d_occ;
     P.rec = p.d_rec;
     P.orig = p.d_orig;
+    P.negcnt = p.d_negcnt;
     P.gfx = p.tab.gfx;
     P.gpad = p.tab.gpad;
     P.fx_scale = std::ldexp(1.0, -p.fx_shift);
@@ -509,11 +811,31 @@ hipError_t launch_sweep_t(const Plan &p, const hp_state &st, int64_t n_sweeps, c
     P.K = p.K;
     P.L = p.L;
     P.B = p.B;
-    // push launch over work items [0, n_push)
+    // push items [0, n_push): one workgroup per chain, or G per chain
     P.lds_v_off = p.push_v_off;
     P.lds_x_off = p.push_x_off;
     P.lds_hm_off = 0;
-    hipError_t e = launch_variant<Real>(true, p.vpt_push, p.n_push, p.lds_push, p.threads, P, s);
+    hipError_t e = hipSuccess;
+    if (p.n_push > 0 && p.split > 1) {
+        SplitParams Q;
+        Q.xpart = p.d_xpart;
+        Q.vbuf = p.d_vbuf;
+        Q.cnt = p.d_cnt;
+        Q.bar = p.d_bar;
+        Q.err = p.d_err;
+        Q.nstride = p.nstride;
+        Q.G = p.split;
+        Q.xcd_map = p.xcd_map;
+        Q.n_xcd = 8;
+        e = launch_zero(p.d_bar, (int64_t)p.n_push * 32, s);
+        if (e != hipSuccess) return e;
+        const int groups = (p.max_n + 3) / 4;
+        const int owned = (groups + p.split - 1) / p.split;
+        if (owned <= p.threads) e = launch_split_one<Real, 1>(p, P, Q, s);
+        else e = launch_split_one<Real, 0>(p, P, Q, s);
+    } else {
+        e = launch_variant<Real>(true, p.vpt_push, p.n_push, p.lds_push, p.threads, P, s);
+    }
     if (e != hipSuccess) return e;
     // pull launch over work items [n_push, n_work)
     P.work = p.d_work + p.n_push;

@@ -7,8 +7,10 @@
 // The key is advanced by the Weyl increments between rounds.
 //
 // The key is uniform across a wavefront (it depends only on the seed and the
-// formula), so the key schedule stays in scalar registers; each round costs
-// two 32x32->64 multiplies and two three-input XORs per lane.
+// formula), so the key schedule stays in scalar registers.  Each round is
+// four VALU instructions per lane: two 32x32->64 multiplies and two
+// three-input XORs (gfx950's v_bitop3_b32 with truth table 0x96 = a^b^c,
+// the key taken straight from its scalar register).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,8 +35,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key2 key) {
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x.z;
-        x = make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
+        x = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x.y, k0, 0x96), (uint32_t)p1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x.w, k1, 0x96), (uint32_t)p0);
     }
     return x;
 }

@@ -20,7 +20,8 @@ HP_FP64, HP_FP32, HP_MIXED_BF16 = 0, 1, 2
 PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
 KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
-EXPORTS = ("hp_plan", "hp_run", "hp_free", "hp_status_string", "hp_last_error")
+EXPORTS = ("hp_plan", "hp_run", "hp_check", "hp_plan_query", "hp_free", "hp_status_string",
+           "hp_last_error")
 
 
 class HpError(RuntimeError):
@@ -44,6 +45,12 @@ class HpOpts(ct.Structure):
     _fields_ = [("chains", ct.c_int32), ("temp_of_chain", ct.POINTER(ct.c_int32)),
                 ("precision", ct.c_int32), ("alpha", ct.c_double), ("seed", ct.c_uint64),
                 ("threads", ct.c_int32), ("split", ct.c_int32), ("kernel", ct.c_int32)]
+
+
+class HpPlanInfo(ct.Structure):
+    _fields_ = [("threads", ct.c_int32), ("split", ct.c_int32), ("push_items", ct.c_int32),
+                ("pull_items", ct.c_int32), ("fx_shift", ct.c_int32), ("reserved", ct.c_int32),
+                ("lds_push", ct.c_int64), ("lds_pull", ct.c_int64)]
 
 
 class HpState(ct.Structure):
@@ -74,6 +81,10 @@ def load():
     lib.hp_plan.restype = ct.c_int
     lib.hp_run.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
     lib.hp_run.restype = ct.c_int
+    lib.hp_plan_query.argtypes = [ct.c_void_p, ct.POINTER(HpPlanInfo)]
+    lib.hp_plan_query.restype = ct.c_int
+    lib.hp_check.argtypes = [ct.c_void_p]
+    lib.hp_check.restype = ct.c_int
     lib.hp_free.argtypes = [ct.c_void_p]
     lib.hp_free.restype = ct.c_int
     lib.hp_status_string.argtypes = [ct.c_int]
@@ -147,6 +158,17 @@ class Plan:
                            _stream_handle(stream)))
         self._h = h
 
+    def info(self):
+        """Launch configuration chosen by the library (dict)."""
+        out = HpPlanInfo()
+        _check(load().hp_plan_query(self._h, ct.byref(out)))
+        return {f: getattr(out, f) for f, _ in HpPlanInfo._fields_ if f != "reserved"}
+
+    @property
+    def split(self):
+        """Workgroups per chain of the push launch."""
+        return self.info()["split"]
+
     @property
     def total_vars(self):
         return int(self.var_offset[-1])
@@ -160,6 +182,10 @@ class Plan:
         lib = load()
         _check(lib.hp_run(self._h, ct.byref(state.c_struct()), int(n_sweeps),
                           _stream_handle(stream)))
+
+    def check(self):
+        """Synchronise and raise if a device-side barrier timed out."""
+        _check(load().hp_check(self._h))
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

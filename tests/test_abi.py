@@ -56,7 +56,7 @@ def _plan_status(lib, tables, ns, W, b, **kw):
     temps = kw.get("temps")
     tp = hp._ptr(np.asarray(temps, np.int32), ct.c_int32) if temps is not None else None
     opts = hp.HpOpts(kw.get("B", 2), tp, kw.get("prec", hp.HP_FP64), kw.get("alpha", 1e-3), 0,
-                     kw.get("threads", 0), 0)
+                     kw.get("threads", 0), kw.get("split", 0), kw.get("kernel", 0))
     h = ct.c_void_p()
     st = lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts), None)
     assert not h.value            # never a partial plan
@@ -77,6 +77,9 @@ CASES = [
     ("bad thread count", dict(threads=100), hp.HP_EINVAL),
     ("unknown precision", dict(prec=7), hp.HP_EINVAL),
     ("mixed precision unavailable", dict(prec=hp.HP_MIXED_BF16), hp.HP_EUNSUPPORTED),
+    ("split not a power of two", dict(split=3), hp.HP_EINVAL),
+    ("split too large", dict(split=32), hp.HP_EINVAL),
+    ("unknown kernel variant", dict(kernel=5), hp.HP_EINVAL),
 ]
 
 
@@ -110,6 +113,8 @@ def test_invalid_tables_rejected(lib):
 def test_run_rejects_null_plan_and_state(lib):
     assert lib.hp_run(None, None, 1, None) == hp.HP_EINVAL
     assert lib.hp_last_error()
+    assert lib.hp_check(None) == hp.HP_EINVAL
+    assert lib.hp_plan_query(None, None) == hp.HP_EINVAL
 
 
 def test_binding_refuses_missing_library(tmp_path, monkeypatch):

@@ -270,3 +270,64 @@ def test_stationary_distribution_on_gpu(hip):
     tv = 0.5 * np.abs(counts / counts.sum() - pi).sum()
     say(f"[stationarity] TV = {tv:.4f}")
     assert tv < 0.01
+
+
+# --------------------------------------------------------------------------
+# Split launch: G workgroups per chain must reproduce the one-workgroup result
+# bit for bit (exact integer partial sums, same random-number addressing)
+# --------------------------------------------------------------------------
+def _run_states(tables, ns, W, b, B, S, prec, seed, **kw):
+    from paper_2311_02101_amd import hp
+    plan = hp.Plan(tables, ns, W, b, chains=B, precision=prec, seed=seed, **kw)
+    st = plan.new_state([wl.initial_state(B, n, seed, tag=f) for f, n in enumerate(ns)])
+    plan.run(st, S)
+    plan.run(st, 0)
+    plan.check()
+    out = [st.formula(f) for f in range(len(tables))]
+    t = st.get_t()
+    plan.free()
+    return out, t
+
+
+def _same(a, b):
+    for fa, fb in zip(a, b):
+        for x, y in zip(fa, fb):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("split,chains", [(2, 64), (4, 64), (8, 16), (16, 8)])
+def test_split_matches_single_workgroup(hip, split, chains):
+    w = wl.config_workload("plain_n4096_b64")
+    W, b = w.W, w.b
+    say(f"[split={split}] n4096 {chains} chains, 20 sweeps")
+    ref, t1 = _run_states(w.tables, w.n_vars, W, b, chains, 20, "f64", w.seed, split=1)
+    got, t2 = _run_states(w.tables, w.n_vars, W, b, chains, 20, "f64", w.seed, split=split)
+    assert t1 == t2 == 20
+    _same(ref, got)
+
+
+def test_split_fp32_and_global_ema_path(hip):
+    n = 4096
+    T = wl.random_formula(n, 31)
+    W, b = wl.gaussian_rbm(2, 7, 8, 31)
+    say("[split fp32, 64 threads] 3 chains (no XCD map), split 4")
+    ref, _ = _run_states([T], [n], W, b, 3, 15, "f32", 31, split=1, threads=64)
+    got, _ = _run_states([T], [n], W, b, 3, 15, "f32", 31, split=4, threads=64)
+    _same(ref, got)
+
+
+def test_split_tiny_ragged_members(hip):
+    """Members that own no variables or no clauses."""
+    clauses = [[[5, -1, 2], [-3, 4], [1], [-5, 2, 3]], [[1, -2], [2]]]
+    tables = [wl.pad_clauses(cl, 3) for cl in clauses]
+    W, b = wl.gaussian_rbm(1, 3, 3, 6)
+    say("[split tiny] N=5,2 split 8")
+    ref, _ = _run_states(tables, [5, 2], W, b, 8, 25, "f64", 6, split=1)
+    got, _ = _run_states(tables, [5, 2], W, b, 8, 25, "f64", 6, split=8)
+    _same(ref, got)
+
+
+def test_split_against_oracle(hip):
+    w = wl.config_workload("plain_n4096_b64")
+    _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 64, 30, "f64", w.seed,
+                chains=[0, 33, 63], label="n4096 fp64 auto split")
