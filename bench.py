@@ -1,12 +1,16 @@
 """Benchmark of the block-Gibbs hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--precision f64|f32]
+    python bench.py [--steps K] [--warmup W] [--precision f64|f32] [--workload NAME]
 
-One step = one instance: the formula N = 4096, C = 24576 (K = 7, L = 8) with
-its 64 chains advanced 500 sweeps (one dispatch of 500 Gibbs rounds, the
-appendix "Batching operations"), inputs resident in HBM before timing.
-Prints ONE JSON line with throughput (instances/s), the ALU roofline of the
-sweep kernel and the CPU oracle baseline timed on a bounded sample.
+Default workload: the formula N = 4096, C = 24576 (K = 7, L = 8) with its 64
+chains.  One step advances every formula of the workload 500 sweeps on all
+its chains (one dispatch of 500 Gibbs rounds, the appendix "Batching
+operations"); an instance is one formula so advanced.  Inputs are resident in
+HBM before timing.  Prints ONE JSON line with throughput (instances/s), the
+ALU roofline of the sweep kernels and the CPU oracle baseline timed on a
+bounded sample.  --workload uneven_1024x64 runs the batch of 1024 formulas of
+log-uniform size 64..16384 (64 chains each) through size-class launches in
+one hipGraph, autotuned first.
 """
 from __future__ import annotations
 
@@ -56,6 +60,8 @@ def main(argv=None):
     ap.add_argument("--split", type=int, default=0, help="workgroups per chain (0 = automatic)")
     ap.add_argument("--cpu-sweeps", type=int, default=10,
                     help="sweeps of the oracle sample (all chains); 0 skips the CPU leg")
+    ap.add_argument("--graph", type=int, default=-1, help="hipGraph replay (default: on for batches)")
+    ap.add_argument("--tune", type=int, default=-1, help="autotune first (default: on for batches)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -69,18 +75,28 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress(f"workload {args.workload}: generating inputs")
     w = wl.config_workload(args.workload, precision=args.precision)
-    N, B = w.n_vars[0], w.chains
-    C = w.tables[0].shape[1]
+    B = w.chains
     L = w.W.shape[2]
+    batch = len(w.n_vars) > 1
+    use_graph = (args.graph if args.graph >= 0 else int(batch)) == 1
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=B, temps=w.temps,
                    precision=args.precision, alpha=w.alpha, seed=w.seed, threads=args.threads,
-                   kernel=args.kernel, split=args.split)
+                   kernel=args.kernel, split=args.split, graph=use_graph)
+    progress(f"planned: {plan.info()['n_buckets']} launch(es)")
+    if (args.tune if args.tune >= 0 else int(batch)) == 1:
+        plan.tune(n_sweeps=3)
+        progress(f"tuned: workgroup sizes {plan.info()['bucket_threads']}")
     st = plan.new_state(w.v0, device=dev)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         plan.run(st, args.sweeps, stream)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        progress(f"warmup step {i + 1}/{args.warmup} done")
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -93,31 +109,40 @@ def main(argv=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plan.check()
+    progress(f"timed {args.steps} steps in {wall:.3f} s")
     launch_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
 
     instances = args.steps * len(w.n_vars)
     value = instances / wall
-    calls, draws, slots = chain_sweep_work(N, C, L)
+    calls = draws = slots = 0
+    for n, t in zip(w.n_vars, w.tables):
+        c1, d1, s1 = chain_sweep_work(n, t.shape[1], L)
+        calls, draws, slots = calls + c1, draws + d1, slots + s1
     per_launch_slots = slots * B * args.sweeps
     achieved = per_launch_slots / avg_launch_s
+    N = w.n_vars[0] if not batch else int(sum(w.n_vars))
+    C = w.tables[0].shape[1] if not batch else int(sum(t.shape[1] for t in w.tables))
     out = {
         "metric": "instances/sec at oracle-matched tolerance; fraction of HBM/MFMA roofline",
         "value": value, "unit": "instances/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": args.workload, "n_vars": N, "clauses": C, "K": 7, "L": L,
+        "config": {"workload": args.workload, "formulas": len(w.n_vars),
+                   "n_vars": N, "clauses": C, "K": 7, "L": L,
                    "chains": B, "sweeps_per_step": args.sweeps, "temperatures": list(wl.FSTAR_PAIR),
+                   "graph": use_graph,
                    "threads": plan_threads(args.threads), "kernel": args.kernel,
                    "launch": plan.info(),
                    "parallelism": "single GPU"},
         "chain_sweeps_per_s": B * args.sweeps * instances / wall,
-        "draws_per_s": draws * B * args.sweeps * instances / wall,
+        "draws_per_s": draws * B * args.sweeps * args.steps / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / PEAK_SLOTS,
                      "traffic": None,
-                     "kernel": "sweep_pull_kernel" if args.kernel == "pull" else "sweep_push_kernel",
+                     "kernel": ("sweep_pull_kernel" if args.kernel == "pull" else
+                                "sweep_split_kernel" if plan.split > 1 else "sweep_push_kernel"),
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "philox_calls_per_chain_sweep": calls, "draws_per_chain_sweep": draws},
     }
@@ -133,32 +158,53 @@ def plan_threads(t):
 
 
 def cpu_baseline(w, plan, sweeps, precision, dev):
-    """Time the oracle (as it stands) on a bounded sample -- all chains of the
-    workload for ``sweeps`` sweeps from the initial state -- and compare the
-    GPU's result for the same sample (parity of the timed configuration)."""
+    """Time the oracle (as it stands) on a bounded sample of the workload and
+    compare the GPU's result for the same sample (parity of the timed
+    configuration).  Single formula: all chains for ``sweeps`` sweeps.
+    Batches: 8 formulas spread over the sizes, 4 chains each, 2 sweeps.
+    The rate is scaled to instances/s of the whole workload by its total
+    chain-sweep work, weighted by formula size."""
     import torch
     from oracle import rbmsat as R
 
-    op = R.plan(w.tables[0], w.n_vars[0], w.W, w.b)
-    ost = R.initial(w.v0[0])
-    t0 = time.perf_counter()
-    R.run(ost, op, w.temps, sweeps, alpha=w.alpha, seed=w.seed)
-    el = time.perf_counter() - t0
-    chain_sweeps = w.chains * sweeps
-    per_instance = el / chain_sweeps * w.chains * 500
+    batch = len(w.n_vars) > 1
+    if batch:
+        order = np.argsort(w.n_vars)
+        pick = [int(order[i]) for i in np.linspace(0, len(order) - 1, 8).astype(int)]
+        chains, sw = np.arange(4), 2
+    else:
+        pick, chains, sw = [0], np.arange(w.chains), sweeps
+    el = 0.0
+    work_done = 0.0
+    parity = {"v_mismatches": 0, "s_max_equal": True, "best_equal": True, "nu_max_rel_err": 0.0}
     st = plan.new_state(w.v0, device=dev)
-    plan.run(st, sweeps)
+    plan.run(st, sw)
     torch.cuda.synchronize()
-    v, nu, s_max, best = st.formula(0)
-    rel = float(np.max(np.abs(nu - ost.nu) / ost.nu))
-    return {"value": 1.0 / per_instance, "unit": "instances/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.chains} chains x {sweeps} sweeps of the same workload "
-                      f"({el:.1f} s single-threaded NumPy FP64), scaled to 500 sweeps",
-            "chain_sweeps_per_s": chain_sweeps / el,
-            "parity": {"v_mismatches": int(np.sum(v != ost.v)),
-                       "s_max_equal": bool(np.array_equal(s_max, ost.s_max)),
-                       "best_equal": bool(np.array_equal(best, ost.best)),
-                       "nu_max_rel_err": rel}}
+    for f in pick:
+        op = R.plan(w.tables[f], w.n_vars[f], w.W, w.b)
+        ost = R.initial(w.v0[f][chains])
+        t0 = time.perf_counter()
+        R.run(ost, op, w.temps[chains], sw, alpha=w.alpha, seed=w.seed, formula_id=f,
+              chain_ids=chains)
+        el += time.perf_counter() - t0
+        work_done += len(chains) * sw * w.n_vars[f]
+        v, nu, s_max, best = st.formula(f)
+        v, nu, s_max, best = v[chains], nu[chains], s_max[chains], best[chains]
+        parity["v_mismatches"] += int(np.sum(v != ost.v))
+        parity["s_max_equal"] &= bool(np.array_equal(s_max, ost.s_max))
+        parity["best_equal"] &= bool(np.array_equal(best, ost.best))
+        parity["nu_max_rel_err"] = max(parity["nu_max_rel_err"],
+                                       float(np.max(np.abs(nu - ost.nu) / ost.nu)))
+    # seconds per (chain-sweep x variable), then per step of the workload
+    rate = el / work_done
+    step_work = w.chains * 500 * float(sum(w.n_vars))
+    per_step = rate * step_work
+    sample = (f"{len(pick)} formulas (N = {sorted(w.n_vars[f] for f in pick)}) x {len(chains)} chains "
+              f"x {sw} sweeps" if batch else f"{w.chains} chains x {sw} sweeps") + \
+        f" of the same workload ({el:.1f} s single-threaded NumPy FP64), scaled to 500 sweeps"
+    return {"value": len(w.n_vars) / per_step, "unit": "instances/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "chain_sweeps_per_s": w.chains * 500 * len(w.n_vars) / per_step,
+            "parity": parity}
 
 
 if __name__ == "__main__":

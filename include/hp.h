@@ -85,6 +85,9 @@ typedef struct {
                                        automatic (fill the device), 1 = one, or a power
                                        of two up to 16 (all must be co-resident)       */
     int32_t kernel;                 /* hp_kernel: sweep kernel variant                 */
+    int32_t graph;                  /* 1: hp_run replays a captured hipGraph of its
+                                       launches (cached per state buffers and sweep
+                                       count); incompatible with split > 1           */
 } hp_opts;
 
 typedef enum {
@@ -139,15 +142,26 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
  * advanced by n_sweeps.  HP_EINVAL if the state does not match the plan. */
 hp_status hp_run(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
 
+/* Autotuner: for every launch of the plan, time each candidate workgroup
+ * size (64..1024) on `n_sweeps` sweeps of the given state and keep the
+ * fastest.  The trial runs overwrite the state's v, nu, s_max and best
+ * without advancing t, so pass a scratch state of the right shape.
+ * Synchronous.  Cached graphs are discarded. */
+hp_status hp_tune(hp_plan_t plan, const hp_state *scratch, int64_t n_sweeps, void *stream);
+
 /* How a plan runs (for reports and tuning). */
 typedef struct {
-    int32_t threads;                /* workgroup size                                 */
+    int32_t threads;                /* largest workgroup size of any launch           */
     int32_t split;                  /* workgroups per chain of the push launch        */
-    int32_t push_items;             /* (formula, chain) items on the push kernel      */
+    int32_t push_items;             /* (formula, chain) items on the push kernels     */
     int32_t pull_items;             /* (formula, chain) items on the pull kernel      */
     int32_t fx_shift;               /* S: push accumulators count units of 2^-S       */
-    int32_t reserved;
-    int64_t lds_push, lds_pull;     /* dynamic LDS bytes per workgroup of each launch */
+    int32_t n_buckets;              /* launches per run (one per size class/variant)  */
+    int64_t lds_push, lds_pull;     /* largest dynamic LDS bytes per workgroup        */
+    /* first 16 launches: variant (0 push, 1 push with global tables, 2 pull),
+     * work items, workgroup size, largest N, persistent grid (0 = one
+     * workgroup per item) */
+    int32_t bucket_kind[16], bucket_items[16], bucket_threads[16], bucket_max_n[16], bucket_grid[16];
 } hp_plan_info;
 
 /* Fill *out with the plan's launch configuration.  HP_EINVAL on NULL. */

@@ -43,6 +43,14 @@ hipError_t upload(T **dst, const std::vector<T> &src, hipStream_t s) {
 
 void release(Plan *p) {
     if (!p) return;
+    for (GraphEntry &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (int i = 0; i < kMaxBuckets; ++i) {
+        if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
+        if (p->ev_join[i]) (void)hipEventDestroy(p->ev_join[i]);
+    }
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    (void)hipFree(p->d_queue);
     (void)hipFree(p->d_fd);
     (void)hipFree(p->d_work);
     (void)hipFree(p->d_lits);
@@ -119,6 +127,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         return fail(HP_EINVAL, "unknown kernel variant");
     if (opts->split < 0 || opts->split > kMaxSplit || (opts->split & (opts->split - 1)))
         return fail(HP_EINVAL, "split must be 0 (automatic) or a power of two up to 16");
+    if (opts->graph && opts->split > 1) return fail(HP_EINVAL, "graph mode does not capture split launches");
     for (int i = 0; i < T * K * L; ++i)
         if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
     for (int i = 0; i < T * L; ++i)
@@ -269,89 +278,128 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
     const size_t real_bytes = opts->precision == HP_FP64 ? 8 : 4;
-    const int threads = opts->threads ? opts->threads : kMaxThreads;
-    p->threads = threads;
+    p->threads = opts->threads;
 
-    // --- kernel variant per formula, work lists (largest formulas first) ---
+    // --- kernel variant and size class per formula, work list, buckets ---
+    // kind: push (G tables in LDS) when everything fits, else push with the
+    // G tables in global memory, else the pull kernel.  Formulas are ordered
+    // by (kind, size class) and, inside a class, largest first; each (kind,
+    // class) run of work items becomes one launch.
+    auto kind_of = [&](int f) -> int {
+        int32_t vo, xo, ho;
+        const bool fx_ok = fx_shift >= 40;
+        if (opts->kernel != HP_KERNEL_PULL && fx_ok) {
+            if (lds_bytes_push(fd[f].n, false, &vo, &xo) <= (size_t)max_lds) return kBucketPush;
+            if (lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds) return kBucketWide;
+        }
+        if (opts->kernel == HP_KERNEL_PUSH) return -1;
+        if (lds_bytes_pull(fd[f].n, fd[f].c, real_bytes, &vo, &ho) <= (size_t)max_lds) return kBucketPull;
+        return -1;
+    };
+    auto size_class = [&](int f) {
+        int c = 0;
+        while (c < 9 && (64 << (c + 1)) <= fd[f].n) ++c;
+        return c;
+    };
+    std::vector<int> kind(F), cls(F);
+    for (int f = 0; f < F; ++f) {
+        kind[f] = kind_of(f);
+        if (kind[f] < 0) {
+            release(p);
+            return fail(HP_EUNSUPPORTED, "formula " + std::to_string(f) + " (N = " + std::to_string(fd[f].n) +
+                                             ") does not fit the workgroup LDS limit (" + std::to_string(max_lds) +
+                                             " B) with the requested kernel");
+        }
+        cls[f] = size_class(f);
+    }
     std::vector<int> order(F);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (kind[a] != kind[b]) return kind[a] < kind[b];
+        if (cls[a] != cls[b]) return cls[a] > cls[b];
         return (int64_t)fd[a].n * 7 + fd[a].c > (int64_t)fd[b].n * 7 + fd[b].c;
     });
-    std::vector<WorkItem> work_push, work_pull;
-    int pn = 0, qn = 0, qc = 0;   // largest N (push), largest N and C (pull)
-    for (int f : order) {
-        int32_t vo, xo, ho;
-        const bool push_ok = fx_shift >= 40 && lds_bytes_push(fd[f].n, &vo, &xo) <= (size_t)max_lds;
-        const bool pull_ok = lds_bytes_pull(fd[f].n, fd[f].c, real_bytes, &vo, &ho) <= (size_t)max_lds;
-        bool use_push;
-        if (opts->kernel == HP_KERNEL_PUSH) {
-            if (!push_ok) {
-                release(p);
-                return fail(HP_EUNSUPPORTED, "push kernel: formula " + std::to_string(f) +
-                                                 " does not fit in LDS (" + std::to_string(max_lds) + " B)");
-            }
-            use_push = true;
-        } else if (opts->kernel == HP_KERNEL_PULL) {
-            use_push = false;
-        } else {
-            use_push = push_ok;
+    std::vector<WorkItem> work;
+    work.reserve((size_t)F * B);
+    for (size_t j = 0; j < order.size(); ++j) {
+        const int f = order[j];
+        if (j == 0 || kind[f] != kind[order[j - 1]] || cls[f] != cls[order[j - 1]]) {
+            Bucket bk;
+            bk.kind = kind[f];
+            bk.first = (int32_t)work.size();
+            p->buckets.push_back(bk);
         }
-        if (!use_push && !pull_ok) {
-            release(p);
-            return fail(HP_EUNSUPPORTED, "formula " + std::to_string(f) +
-                                             ": working set exceeds the workgroup LDS limit (" +
-                                             std::to_string(max_lds) + " B)");
-        }
-        for (int b = 0; b < B; ++b) (use_push ? work_push : work_pull).push_back({f, b});
-        if (use_push) pn = std::max(pn, fd[f].n);
-        else { qn = std::max(qn, fd[f].n); qc = std::max(qc, fd[f].c); }
+        Bucket &bk = p->buckets.back();
+        bk.max_n = std::max(bk.max_n, fd[f].n);
+        bk.max_c = std::max(bk.max_c, fd[f].c);
+        for (int b = 0; b < B; ++b) work.push_back({f, b});
+        bk.count = (int32_t)work.size() - bk.first;
     }
-    auto vpt_for = [&](int n) {
-        const int groups = (n + 3) / 4;
-        int v = 1;
-        while (v * threads < groups) v *= 2;
-        return v;
-    };
-    p->n_push = (int32_t)work_push.size();
-    p->vpt_push = vpt_for(pn);
-    p->vpt_pull = vpt_for(qn);
-    p->lds_push = work_push.empty() ? 0 : lds_bytes_push(pn, &p->push_v_off, &p->push_x_off);
-    p->lds_pull = work_pull.empty() ? 0 : lds_bytes_pull(qn, qc, real_bytes, &p->pull_v_off, &p->pull_hm_off);
-    std::vector<WorkItem> work(work_push);
-    work.insert(work.end(), work_pull.begin(), work_pull.end());
+    if ((int)p->buckets.size() > kMaxBuckets) {
+        release(p);
+        return fail(HP_EUNSUPPORTED, "too many size classes");
+    }
     p->n_work = (int32_t)work.size();
-
-    // --- split: G co-resident workgroups per chain for the push items ---
-    int cus = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
-    int min_c = INT32_MAX;
-    for (const WorkItem &it : work_push) min_c = std::min(min_c, fd[it.f].c);
+    e = set_kernel_lds_limits(max_lds);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "hipFuncSetAttribute"); }
+    for (Bucket &bk : p->buckets) {
+        if (bk.kind == kBucketPull)
+            bk.lds = lds_bytes_pull(bk.max_n, bk.max_c, real_bytes, &bk.v_off, &bk.hm_off);
+        else
+            bk.lds = lds_bytes_push(bk.max_n, bk.kind == kBucketWide, &bk.v_off, &bk.x_off);
+        // default workgroup size: about six clauses per thread per sweep
+        int t = opts->threads;
+        if (t == 0) {
+            t = 64;
+            while (t < kMaxThreads && t * 6 < bk.max_c) t *= 2;
+        }
+        bk.threads = t;
+        const int groups = (bk.max_n + 3) / 4;
+        bk.vpt = groups <= t ? 1 : (groups <= 2 * t ? 2 : 0);
+        // persistent grid when the items outnumber the resident workgroups
+        const int occ = bucket_occupancy(*p, bk);
+        const int64_t capacity = (int64_t)p->cus * std::max(occ, 1);
+        bk.grid = (bk.kind != kBucketPull && bk.count > capacity) ? (int32_t)capacity : 0;
+    }
+
+    // --- split: G co-resident workgroups per chain, single push bucket only ---
     int G = 1;
-    if (p->n_push > 0 && opts->split != 1) {
+    const bool single_push = p->buckets.size() == 1 && p->buckets[0].kind == kBucketPush;
+    if (opts->split >= 2 && !single_push) {
+        release(p);
+        return fail(HP_EUNSUPPORTED, "split needs a batch whose formulas all share one push launch");
+    }
+    if (single_push && opts->split != 1 && !opts->graph) {
+        Bucket &bk = p->buckets[0];
+        const int saved = bk.threads;
+        if (opts->threads == 0) bk.threads = kMaxThreads;
         const int occ = split_occupancy(*p);
-        const int64_t capacity = (int64_t)cus * occ;
+        const int64_t capacity = (int64_t)p->cus * occ;
+        const int n_items = bk.count;
         if (opts->split >= 2) {
             G = opts->split;
-            if ((int64_t)p->n_push * G > capacity) {
+            if ((int64_t)n_items * G > capacity) {
                 release(p);
                 return fail(HP_EUNSUPPORTED, "split " + std::to_string(G) + ": " +
-                                                 std::to_string((int64_t)p->n_push * G) +
+                                                 std::to_string((int64_t)n_items * G) +
                                                  " workgroups cannot all be resident (capacity " +
                                                  std::to_string(capacity) + ")");
             }
         } else {
             // largest power of two that keeps every workgroup resident and
             // leaves each member at least 1024 clauses
-            while (G * 2 <= kMaxSplit && (int64_t)p->n_push * G * 2 <= capacity &&
-                   min_c / (G * 2) >= 1024)
+            while (G * 2 <= kMaxSplit && (int64_t)n_items * G * 2 <= capacity && bk.max_c / (G * 2) >= 1024)
                 G *= 2;
         }
+        if (G == 1) bk.threads = saved;   // no split: keep the bucket's own shape
+        else bk.grid = 0;                 // split launches run one item per group
     }
     p->split = G;
-    p->nstride = ((int64_t)pn + 15) / 16 * 16;
-    p->xcd_map = (p->n_push % 8 == 0) ? 1 : 0;
+    p->nstride = ((int64_t)p->buckets[0].max_n + 15) / 16 * 16;
+    p->xcd_map = (p->buckets[0].count % 8 == 0) ? 1 : 0;
+    p->use_graph = opts->graph ? 1 : 0;
 
     // --- device upload ---
     hipStream_t s = (hipStream_t)stream;
@@ -385,8 +433,17 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_err), 1, s), "clear error flag");
     HP_TRY(hipMalloc((void **)&p->d_tabflag, sizeof(int32_t)), "alloc table flag");
     HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_tabflag), 1, s), "clear table flag");
+    HP_TRY(hipMalloc((void **)&p->d_queue, kMaxBuckets * 32 * sizeof(uint32_t)), "alloc work counters");
+    for (size_t i = 0; i < p->buckets.size() && p->buckets.size() > 1; ++i)
+        HP_TRY(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking), "side stream");
+    if (p->buckets.size() > 1) {
+        HP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "event");
+        for (size_t i = 0; i < p->buckets.size(); ++i)
+            HP_TRY(hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming), "event");
+    }
+    if (p->use_graph) HP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
     if (p->split > 1) {
-        const size_t items = (size_t)p->n_push;
+        const size_t items = (size_t)p->buckets[0].count;
         HP_TRY(hipMalloc((void **)&p->d_xpart, items * p->split * p->nstride * sizeof(int64_t)), "alloc xpart");
         HP_TRY(hipMalloc((void **)&p->d_vbuf, items * p->nstride), "alloc vbuf");
         HP_TRY(hipMalloc((void **)&p->d_cnt, items * kMaxSplit * sizeof(int32_t)), "alloc counts");
@@ -420,8 +477,86 @@ hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *str
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != p->device) return fail(HP_EINVAL, "plan was built on another device");
-    e = launch_sweep(*p, *st, n_sweeps, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    if (!p->use_graph) {
+        e = launch_sweep(*p, *st, n_sweeps, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "sweep launch");
+        return HP_OK;
+    }
+    // graph mode: capture the run's launches once per (state buffers, sweep
+    // count) on a private stream, then replay the instantiated graph on the
+    // caller's stream
+    GraphEntry *ge = nullptr;
+    for (GraphEntry &g : p->graphs)
+        if (g.v == st->v && g.nu == st->nu && g.s_max == st->s_max && g.best == st->best && g.t == st->t &&
+            g.n_sweeps == n_sweeps)
+            ge = &g;
+    if (!ge) {
+        e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = launch_sweep(*p, *st, n_sweeps, p->cap_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(p->cap_stream, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le != hipSuccess ? le : e, "graph capture");
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        p->graphs.push_back({st->v, st->nu, st->s_max, st->best, st->t, n_sweeps, exec});
+        ge = &p->graphs.back();
+    }
+    e = hipGraphLaunch(ge->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return HP_OK;
+}
+
+hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !st) return fail(HP_EINVAL, "null argument");
+    if (n_sweeps < 1) return fail(HP_EINVAL, "n_sweeps must be >= 1");
+    if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B ||
+        st->nu_bytes != (p->precision == HP_FP64 ? 8 : 4))
+        return fail(HP_EINVAL, "state shape does not match the plan");
+    if (p->split > 1) return HP_OK;    // the split launch keeps its full-size workgroups
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (Bucket &bk : p->buckets) {
+        if (e != hipSuccess) break;
+        const Bucket orig = bk;
+        float best_ms = -1.0f;
+        Bucket best = bk;
+        for (int t = 64; t <= kMaxThreads && e == hipSuccess; t *= 2) {
+            bk = orig;
+            bk.threads = t;
+            const int groups = (bk.max_n + 3) / 4;
+            bk.vpt = groups <= t ? 1 : (groups <= 2 * t ? 2 : 0);
+            const int occ = bucket_occupancy(*p, bk);
+            if (occ < 1) continue;     // this shape cannot launch
+            const int64_t capacity = (int64_t)p->cus * occ;
+            bk.grid = (bk.kind != kBucketPull && bk.count > capacity) ? (int32_t)capacity : 0;
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_bucket(*p, bk, *st, n_sweeps, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best = bk;
+            }
+        }
+        bk = best_ms < 0.0f ? orig : best;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "hp_tune");
+    for (GraphEntry &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
     return HP_OK;
 }
 
@@ -429,14 +564,24 @@ hp_status hp_plan_query(hp_plan_t plan, hp_plan_info *out) {
     g_last_error.clear();
     const Plan *p = reinterpret_cast<const Plan *>(plan);
     if (!p || !out) return fail(HP_EINVAL, "null argument");
-    out->threads = p->threads;
+    std::memset(out, 0, sizeof(*out));
     out->split = p->split;
-    out->push_items = p->n_push;
-    out->pull_items = p->n_work - p->n_push;
     out->fx_shift = p->fx_shift;
-    out->reserved = 0;
-    out->lds_push = (int64_t)p->lds_push;
-    out->lds_pull = (int64_t)p->lds_pull;
+    out->n_buckets = (int32_t)p->buckets.size();
+    for (size_t i = 0; i < p->buckets.size(); ++i) {
+        const Bucket &b = p->buckets[i];
+        (b.kind == kBucketPull ? out->pull_items : out->push_items) += b.count;
+        if (b.kind == kBucketPull) out->lds_pull = std::max<int64_t>(out->lds_pull, (int64_t)b.lds);
+        else out->lds_push = std::max<int64_t>(out->lds_push, (int64_t)b.lds);
+        out->threads = std::max(out->threads, b.threads);
+        if (i < 16) {
+            out->bucket_kind[i] = b.kind;
+            out->bucket_items[i] = b.count;
+            out->bucket_threads[i] = b.threads;
+            out->bucket_max_n[i] = b.max_n;
+            out->bucket_grid[i] = b.grid;
+        }
+    }
     return HP_OK;
 }
 

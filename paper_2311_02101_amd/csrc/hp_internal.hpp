@@ -110,6 +110,27 @@ struct SplitParams {
 
 enum class Variant { kPull = 0, kPush = 1 };
 
+// A launch over a contiguous range of work items: formulas of one size class
+// and one kernel variant, with its own workgroup size and LDS footprint.
+enum BucketKind : int32_t { kBucketPush = 0, kBucketWide = 1, kBucketPull = 2 };
+constexpr int kMaxBuckets = 32;
+
+struct Bucket {
+    int32_t kind = kBucketPush;
+    int32_t first = 0, count = 0;   // work items [first, first + count)
+    int32_t threads = 0, vpt = 1;   // workgroup size, visible groups per thread
+    int32_t max_n = 0, max_c = 0;
+    size_t lds = 0;
+    int32_t v_off = 0, x_off = 0, hm_off = 0;
+    int32_t grid = 0;               // persistent grid (0: one workgroup per item)
+};
+
+struct GraphEntry {
+    void *v, *nu, *s_max, *best, *t;
+    int64_t n_sweeps;
+    hipGraphExec_t exec;
+};
+
 struct Plan {
     int32_t F = 0, K = 0, L = 0, T = 0, B = 0;
     int32_t precision = HP_FP64;
@@ -117,20 +138,21 @@ struct Plan {
     uint64_t seed = 0;
     int64_t total_vars = 0, total_clauses = 0, total_occ = 0;
     int32_t max_n = 0, max_c = 0;
-    int32_t threads = 0;
+    int32_t threads = 0;         // workgroup size override (0 = per bucket)
     int32_t fx_shift = 0;        // S of the fixed-point accumulators
-    // two launches: formulas whose accumulators fit in LDS use the push
-    // kernel (work items [0, n_push)), the others the pull kernel
-    // (items [n_push, n_work)); each launch is sized for its largest formula
-    int32_t n_push = 0;
-    int32_t vpt_push = 0, vpt_pull = 0;   // visible groups of 4 per thread
-    size_t lds_push = 0, lds_pull = 0;
-    int32_t push_v_off = 0, push_x_off = 0;
-    int32_t pull_v_off = 0, pull_hm_off = 0;
-    int32_t split = 1;           // G workgroups per chain for the push items
+    int32_t cus = 0;             // compute units of the device
+    std::vector<Bucket> buckets;
+    int32_t split = 1;           // G workgroups per chain (single push bucket only)
     int32_t xcd_map = 0;
     int64_t nstride = 0;
+    int32_t use_graph = 0;
     int device = 0;
+    hipStream_t side[kMaxBuckets] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[kMaxBuckets] = {};
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    uint32_t *d_queue = nullptr;     // [kMaxBuckets * 32] persistent work counters
     // device memory
     FormulaDev *d_fd = nullptr;
     WorkItem *d_work = nullptr;
@@ -156,6 +178,12 @@ struct Plan {
 // kernels / launchers (hp_kernels.hip)
 hipError_t launch_tables(const Plan &p, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s);
+// one bucket alone (no fork/join, no counter advance): used by the tuner
+hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s);
+// raise the dynamic-LDS limit of every sweep kernel to `bytes` (once per plan)
+hipError_t set_kernel_lds_limits(int bytes);
+// resident workgroups per CU of a bucket's kernel at its launch shape
+int bucket_occupancy(const Plan &p, const Bucket &b);
 
 hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t s);
 
@@ -164,7 +192,7 @@ int split_occupancy(const Plan &p);
 
 // LDS bytes of the two kernel variants for the largest formula
 size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);
-size_t lds_bytes_push(int max_n, int32_t *v_off, int32_t *x_off);
+size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off);
 
 void set_error(const std::string &msg);
 

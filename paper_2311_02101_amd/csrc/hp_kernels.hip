@@ -37,6 +37,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace hp {
 
@@ -145,8 +146,12 @@ constexpr int kPushGpadOff = kPushGfxOff + kHidMasks * kMaxL * 8;
 constexpr int kPushCntOff = kPushGpadOff + kMaxL * kHidMasks * 8;
 constexpr int kPushXOff = kPushCntOff + 64 * 4;
 
-size_t lds_bytes_push(int max_n, int32_t *v_off, int32_t *x_off) {
-    size_t off = kPushXOff;
+// wide layout (G tables read from global memory): thr | counts | x | v
+constexpr int kWideCntOff = kPatterns * kMaxL * 4;
+constexpr int kWideXOff = kWideCntOff + 64 * 4;
+
+size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off) {
+    size_t off = wide ? kWideXOff : kPushXOff;
     *x_off = (int32_t)off;
     off += (size_t)max_n * 8;
     *v_off = (int32_t)off;
@@ -338,12 +343,24 @@ __device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off, int v
                    reinterpret_cast<int64_t *>(lds + x_off), lds + v_off};
 }
 
+// wide variant: the G tables of temperature tau stay in global memory
+__device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, int v_off, const int64_t *gfx,
+                                                 const int64_t *gpad, int tau) {
+    return PushLds{reinterpret_cast<uint32_t *>(lds), const_cast<int64_t *>(gfx + tau * kHidMasks * kMaxL),
+                   const_cast<int64_t *>(gpad + tau * kHidMasks * kMaxL),
+                   reinterpret_cast<int *>(lds + kWideCntOff), reinterpret_cast<int64_t *>(lds + x_off),
+                   lds + v_off};
+}
+
+template <bool kWide>
 __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_t *thr, const int64_t *gfx,
                                                  const int64_t *gpad, int tau, int tid, int NT) {
     for (int i = tid; i < kPatterns * kMaxL; i += NT) L.thr[i] = thr[tau * kPatterns * kMaxL + i];
-    for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
-        L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
-        L.gpad[i] = gpad[tau * kHidMasks * kMaxL + i];
+    if (!kWide) {
+        for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
+            L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
+            L.gpad[i] = gpad[tau * kHidMasks * kMaxL + i];
+        }
     }
 }
 
@@ -423,20 +440,15 @@ __device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, i
     return total;
 }
 
-template <typename Real, int VPT>
-__global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
+// One chain per workgroup at a time.  queue == nullptr: workgroup w runs
+// item w.  Otherwise the grid is persistent: workgroups take items from an
+// atomic counter (zeroed before the launch) until all `count` items are done,
+// largest formulas first, so uneven sizes balance over the resident grid.
+template <typename Real, int VPT, bool kWide>
+__global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, uint32_t *queue, int count) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const PushLds L = push_lds(lds, P.lds_x_off, P.lds_v_off);
-
-    const WorkItem w = P.work[blockIdx.x];
-    const FormulaDev fd = P.fd[w.f];
-    const int N = fd.n, C = fd.c;
+    int *s_item = reinterpret_cast<int *>(lds + (kWide ? kWideCntOff : kPushCntOff)) + 63;
     const int tid = threadIdx.x, NT = blockDim.x;
-    const int tau = P.temp_of_chain[w.b];
-    const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
-    const uint4 *__restrict__ rec = P.rec + fd.clause_off;
-    const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
-    const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
     const bool sample = P.n_sweeps > 0;
     const int64_t S = sample ? P.n_sweeps : 1;
     const uint32_t nbh = (uint32_t)(P.L + 3) >> 2;
@@ -444,83 +456,108 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P) {
     const uint32_t lmask = (1u << P.L) - 1u;
     const Real alpha = P.alpha;
     const double fx_scale = P.fx_scale;
-    const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
-
-    load_push_tables(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
-    for (int i = tid; i < N; i += NT) {
-        L.v[i] = P.v[sbase + i];
-        L.x[i] = negcnt[i];
-    }
-    constexpr int VR = VPT > 0 ? VPT : 1;
-    Real nu[VR][4];
-    int32_t ncr[VR][4];
-    if (VPT > 0) {
-#pragma unroll
-        for (int j = 0; j < VR; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = (tid + j * NT) * 4 + q;
-                nu[j][q] = i < N ? P.nu[sbase + i] : Real(0);
-                ncr[j][q] = i < N ? negcnt[i] : 0;
-            }
-    }
-    int smax = P.s_max[(int64_t)w.f * P.B + w.b];
     const int64_t t0 = *P.t_ptr;
-    __syncthreads();
 
-    for (int64_t s = 0; s < S; ++s) {
-        const uint64_t t = (uint64_t)(t0 + s);
-        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-        const int cnt = sample ? clause_phase<true>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
-                               : clause_phase<false>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
-        const int total = block_total(L, cnt, tid, NT);
-        const bool improved = total > smax;
-        if (improved) smax = total;
-        // ---- visible phase ----
-        const int groups = (N + 3) >> 2;
-        const int jmax = VPT > 0 ? VPT : (groups + NT - 1) / NT;
+    for (int it = 0;; ++it) {
+        int item;
+        if (queue == nullptr) {
+            if (it > 0) break;
+            item = blockIdx.x;
+        } else {
+            if (tid == 0) *s_item = (int)atomicAdd(queue, 1u);
+            __syncthreads();
+            item = *s_item;
+            __syncthreads();          // s_item is rewritten by the next take
+            if (item >= count) break;
+        }
+        const WorkItem w = P.work[item];
+        const FormulaDev fd = P.fd[w.f];
+        const int N = fd.n, C = fd.c;
+        const int tau = P.temp_of_chain[w.b];
+        const PushLds L = kWide ? push_lds_wide(lds, P.lds_x_off, P.lds_v_off, P.gfx, P.gpad, tau)
+                                : push_lds(lds, P.lds_x_off, P.lds_v_off);
+        const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
+        const uint4 *__restrict__ rec = P.rec + fd.clause_off;
+        const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
+        const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
+        const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
+
+        load_push_tables<kWide>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+        for (int i = tid; i < N; i += NT) {
+            L.v[i] = P.v[sbase + i];
+            L.x[i] = negcnt[i];
+        }
+        constexpr int VR = VPT > 0 ? VPT : 1;
+        Real nu[VR][4];
+        int32_t ncr[VR][4];
+        if (VPT > 0) {
 #pragma unroll
-        for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
-          for (int jj = (VPT > 0 ? j : 0); jj < (VPT > 0 ? j + 1 : jmax); ++jj) {
-            const int grp = tid + jj * NT;
-            if (grp < groups) {
-                uint4 r = make_uint4(0, 0, 0, 0);
-                if (sample) r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseVisible | (uint32_t)grp, thi), key);
-                const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+            for (int j = 0; j < VR; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int i = grp * 4 + q;
-                    if (i < N) {
-                        if (improved) P.best[sbase + i] = L.v[i];
-                        if (sample) {
-                            const int64_t xi = L.x[i];
-                            L.x[i] = VPT > 0 ? ncr[j][q] : negcnt[i];
-                            if (VPT > 0) {
-                                L.v[i] = visible_update(xi, fx_scale, nu[j][q], alpha, rw[q]);
-                            } else {
-                                Real nv = P.nu[sbase + i];
-                                L.v[i] = visible_update(xi, fx_scale, nv, alpha, rw[q]);
-                                P.nu[sbase + i] = nv;
+                    const int i = (tid + j * NT) * 4 + q;
+                    nu[j][q] = i < N ? P.nu[sbase + i] : Real(0);
+                    ncr[j][q] = i < N ? negcnt[i] : 0;
+                }
+        }
+        int smax = P.s_max[(int64_t)w.f * P.B + w.b];
+        __syncthreads();
+
+        for (int64_t s = 0; s < S; ++s) {
+            const uint64_t t = (uint64_t)(t0 + s);
+            const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+            const int cnt = sample ? clause_phase<true>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
+                                   : clause_phase<false>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
+            const int total = block_total(L, cnt, tid, NT);
+            const bool improved = total > smax;
+            if (improved) smax = total;
+            // ---- visible phase ----
+            const int groups = (N + 3) >> 2;
+            const int jmax = VPT > 0 ? VPT : (groups + NT - 1) / NT;
+#pragma unroll
+            for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
+              for (int jj = (VPT > 0 ? j : 0); jj < (VPT > 0 ? j + 1 : jmax); ++jj) {
+                const int grp = tid + jj * NT;
+                if (grp < groups) {
+                    uint4 r = make_uint4(0, 0, 0, 0);
+                    if (sample) r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseVisible | (uint32_t)grp, thi), key);
+                    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = grp * 4 + q;
+                        if (i < N) {
+                            if (improved) P.best[sbase + i] = L.v[i];
+                            if (sample) {
+                                const int64_t xi = L.x[i];
+                                L.x[i] = VPT > 0 ? ncr[j][q] : negcnt[i];
+                                if (VPT > 0) {
+                                    L.v[i] = visible_update(xi, fx_scale, nu[j][q], alpha, rw[q]);
+                                } else {
+                                    Real nv = P.nu[sbase + i];
+                                    L.v[i] = visible_update(xi, fx_scale, nv, alpha, rw[q]);
+                                    P.nu[sbase + i] = nv;
+                                }
                             }
                         }
                     }
                 }
+              }
             }
-          }
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    for (int i = tid; i < N; i += NT) P.v[sbase + i] = L.v[i];
-    if (VPT > 0) {
+        for (int i = tid; i < N; i += NT) P.v[sbase + i] = L.v[i];
+        if (VPT > 0) {
 #pragma unroll
-        for (int j = 0; j < VR; ++j)
+            for (int j = 0; j < VR; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = (tid + j * NT) * 4 + q;
-                if (i < N) P.nu[sbase + i] = nu[j][q];
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const int i = (tid + j * NT) * 4 + q;
+                    if (i < N) P.nu[sbase + i] = nu[j][q];
+                }
+        }
+        if (tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;
+        __syncthreads();              // LDS is reused by the next item
     }
-    if (tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;
 }
 
 // --------------------------------------------------------------------------
@@ -616,7 +653,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     int32_t *pcnt = Q.cnt + (size_t)item * kMaxSplit;
     uint32_t *ctr = Q.bar + (size_t)item * 32;
 
-    load_push_tables(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+    load_push_tables<false>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
         L.v[i] = P.v[sbase + i];
         L.x[i] = 0;
@@ -730,26 +767,6 @@ __global__ void advance_t_kernel(int64_t *t, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) t[0] += n;
 }
 
-template <typename Real, int VPT>
-hipError_t launch_one(bool push, int n_items, size_t lds, int threads, SweepParams<Real> P, hipStream_t s) {
-    auto kern = push ? sweep_push_kernel<Real, VPT> : sweep_pull_kernel<Real, VPT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(threads), lds, s, P);
-    return hipGetLastError();
-}
-
-template <typename Real>
-hipError_t launch_variant(bool push, int vpt, int n_items, size_t lds, int threads,
-                          const SweepParams<Real> &P, hipStream_t s) {
-    if (n_items == 0) return hipSuccess;
-    switch (vpt) {
-        case 1: return launch_one<Real, 1>(push, n_items, lds, threads, P, s);
-        case 2: return launch_one<Real, 2>(push, n_items, lds, threads, P, s);
-        default: return launch_one<Real, 0>(push, n_items, lds, threads, P, s);
-    }
-}
-
 hipError_t launch_zero(uint32_t *ptr, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
@@ -757,32 +774,75 @@ hipError_t launch_zero(uint32_t *ptr, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename Real>
+const void *push_kernel_ptr(int vpt, bool wide) {
+    switch (vpt) {
+        case 1: return wide ? (const void *)sweep_push_kernel<Real, 1, true> : (const void *)sweep_push_kernel<Real, 1, false>;
+        case 2: return wide ? (const void *)sweep_push_kernel<Real, 2, true> : (const void *)sweep_push_kernel<Real, 2, false>;
+        default: return wide ? (const void *)sweep_push_kernel<Real, 0, true> : (const void *)sweep_push_kernel<Real, 0, false>;
+    }
+}
+
+template <typename Real>
+const void *pull_kernel_ptr(int vpt) {
+    switch (vpt) {
+        case 1: return (const void *)sweep_pull_kernel<Real, 1>;
+        case 2: return (const void *)sweep_pull_kernel<Real, 2>;
+        default: return (const void *)sweep_pull_kernel<Real, 0>;
+    }
+}
+
+template <typename Real>
+hipError_t set_limits_t(int bytes) {
+    const void *ks[] = {push_kernel_ptr<Real>(1, false), push_kernel_ptr<Real>(2, false), push_kernel_ptr<Real>(0, false),
+                        push_kernel_ptr<Real>(1, true),  push_kernel_ptr<Real>(2, true),  push_kernel_ptr<Real>(0, true),
+                        pull_kernel_ptr<Real>(1),        pull_kernel_ptr<Real>(2),        pull_kernel_ptr<Real>(0),
+                        (const void *)sweep_split_kernel<Real, 1>, (const void *)sweep_split_kernel<Real, 0>};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t set_kernel_lds_limits(int bytes) {
+    hipError_t e = set_limits_t<double>(bytes);
+    return e != hipSuccess ? e : set_limits_t<float>(bytes);
+}
+
+int bucket_occupancy(const Plan &p, const Bucket &b) {
+    const void *k;
+    if (b.kind == kBucketPull)
+        k = p.precision == HP_FP64 ? pull_kernel_ptr<double>(b.vpt) : pull_kernel_ptr<float>(b.vpt);
+    else
+        k = p.precision == HP_FP64 ? push_kernel_ptr<double>(b.vpt, b.kind == kBucketWide)
+                                   : push_kernel_ptr<float>(b.vpt, b.kind == kBucketWide);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, b.threads, b.lds) != hipSuccess) return 1;
+    return nb;
+}
+
 int split_occupancy(const Plan &p) {
     int nb = 0;
     const void *kern = p.precision == HP_FP64 ? (const void *)sweep_split_kernel<double, 1>
                                                : (const void *)sweep_split_kernel<float, 1>;
-    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_push) != hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, p.threads, p.lds_push) != hipSuccess) return 0;
+    const Bucket &b = p.buckets[0];
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, b.threads, b.lds) != hipSuccess) return 0;
     return nb;
 }
 
 template <typename Real, int VPT>
 hipError_t launch_split_one(const Plan &p, SweepParams<Real> P, SplitParams Q, hipStream_t s) {
-    auto kern = sweep_split_kernel<Real, VPT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)p.lds_push);
-    if (e != hipSuccess) return e;
+    const Bucket &b = p.buckets[0];
     void *args[] = {(void *)&P, (void *)&Q};
     // cooperative launch: fails instead of running if the G workgroups of a
     // chain could not all be resident at once
-    return hipLaunchCooperativeKernel((const void *)kern, dim3(p.n_push * p.split), dim3(p.threads), args,
-                                      (unsigned)p.lds_push, s);
+    return hipLaunchCooperativeKernel((const void *)sweep_split_kernel<Real, VPT>, dim3(b.count * p.split),
+                                      dim3(b.threads), args, (unsigned)b.lds, s);
 }
 
 template <typename Real>
-hipError_t launch_sweep_t(const Plan &p, const hp_state &st, int64_t n_sweeps, const Real *G,
-                          hipStream_t s) {
+SweepParams<Real> sweep_params(const Plan &p, const hp_state &st, int64_t n_sweeps) {
     SweepParams<Real> P;
     P.fd = p.d_fd;
     P.work = p.d_work;
@@ -796,7 +856,8 @@ hipError_t launch_sweep_t(const Plan &p, const hp_state &st, int64_t n_sweeps, c
     P.gpad = p.tab.gpad;
     P.fx_scale = std::ldexp(1.0, -p.fx_shift);
     P.thr = p.tab.thr;
-    P.G = G;
+    P.G = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(p.tab.g64)
+                                            : reinterpret_cast<const Real *>(p.tab.g32);
     P.temp_of_chain = p.d_temp;
     P.v = st.v;
     P.nu = reinterpret_cast<Real *>(st.nu);
@@ -811,49 +872,90 @@ hipError_t launch_sweep_t(const Plan &p, const hp_state &st, int64_t n_sweeps, c
     P.K = p.K;
     P.L = p.L;
     P.B = p.B;
-    // push items [0, n_push): one workgroup per chain, or G per chain
-    P.lds_v_off = p.push_v_off;
-    P.lds_x_off = p.push_x_off;
-    P.lds_hm_off = 0;
-    hipError_t e = hipSuccess;
-    if (p.n_push > 0 && p.split > 1) {
-        SplitParams Q;
-        Q.xpart = p.d_xpart;
-        Q.vbuf = p.d_vbuf;
-        Q.cnt = p.d_cnt;
-        Q.bar = p.d_bar;
-        Q.err = p.d_err;
-        Q.nstride = p.nstride;
-        Q.G = p.split;
-        Q.xcd_map = p.xcd_map;
-        Q.n_xcd = 8;
-        e = launch_zero(p.d_bar, (int64_t)p.n_push * 32, s);
-        if (e != hipSuccess) return e;
-        const int groups = (p.max_n + 3) / 4;
-        const int owned = (groups + p.split - 1) / p.split;
-        if (owned <= p.threads) e = launch_split_one<Real, 1>(p, P, Q, s);
-        else e = launch_split_one<Real, 0>(p, P, Q, s);
-    } else {
-        e = launch_variant<Real>(true, p.vpt_push, p.n_push, p.lds_push, p.threads, P, s);
+    P.lds_v_off = P.lds_x_off = P.lds_hm_off = 0;
+    return P;
+}
+
+template <typename Real>
+hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+    if (b.count == 0) return hipSuccess;
+    SweepParams<Real> P = sweep_params<Real>(p, st, n_sweeps);
+    P.work = p.d_work + b.first;
+    P.lds_v_off = b.v_off;
+    P.lds_x_off = b.x_off;
+    P.lds_hm_off = b.hm_off;
+    if (b.kind == kBucketPull) {
+        hipLaunchKernelGGL((void (*)(SweepParams<Real>))pull_kernel_ptr<Real>(b.vpt), dim3(b.count), dim3(b.threads),
+                           b.lds, s, P);
+        return hipGetLastError();
     }
+    const bool wide = b.kind == kBucketWide;
+    uint32_t *queue = nullptr;
+    int grid = b.count;
+    if (b.grid > 0) {
+        // the bucket's work counter sits on its own 128-byte line
+        queue = p.d_queue + 32 * (size_t)(&b - p.buckets.data());
+        hipError_t e = launch_zero(queue, 1, s);
+        if (e != hipSuccess) return e;
+        grid = b.grid;
+    }
+    hipLaunchKernelGGL((void (*)(SweepParams<Real>, uint32_t *, int))push_kernel_ptr<Real>(b.vpt, wide), dim3(grid),
+                       dim3(b.threads), b.lds, s, P, queue, b.count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+    return p.precision == HP_FP64 ? launch_bucket_t<double>(p, b, st, n_sweeps, s)
+                                  : launch_bucket_t<float>(p, b, st, n_sweeps, s);
+}
+
+template <typename Real>
+hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+    const Bucket &b = p.buckets[0];
+    SweepParams<Real> P = sweep_params<Real>(p, st, n_sweeps);
+    P.lds_v_off = b.v_off;
+    P.lds_x_off = b.x_off;
+    SplitParams Q;
+    Q.xpart = p.d_xpart;
+    Q.vbuf = p.d_vbuf;
+    Q.cnt = p.d_cnt;
+    Q.bar = p.d_bar;
+    Q.err = p.d_err;
+    Q.nstride = p.nstride;
+    Q.G = p.split;
+    Q.xcd_map = p.xcd_map;
+    Q.n_xcd = 8;
+    hipError_t e = launch_zero(p.d_bar, (int64_t)b.count * 32, s);
     if (e != hipSuccess) return e;
-    // pull launch over work items [n_push, n_work)
-    P.work = p.d_work + p.n_push;
-    P.lds_v_off = p.pull_v_off;
-    P.lds_hm_off = p.pull_hm_off;
-    P.lds_x_off = 0;
-    e = launch_variant<Real>(false, p.vpt_pull, p.n_work - p.n_push, p.lds_pull, p.threads, P, s);
+    const int groups = (b.max_n + 3) / 4;
+    const int owned = (groups + p.split - 1) / p.split;
+    return owned <= b.threads ? launch_split_one<Real, 1>(p, P, Q, s) : launch_split_one<Real, 0>(p, P, Q, s);
+}
+
+// All launches of one run: a split launch, one bucket on the caller's
+// stream, or several buckets forked onto side streams (they are independent)
+// and joined back; then the sweep counter advances.
+hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (p.split > 1) {
+        e = p.precision == HP_FP64 ? launch_split_t<double>(p, st, n_sweeps, s) : launch_split_t<float>(p, st, n_sweeps, s);
+    } else if (p.buckets.size() == 1) {
+        e = launch_bucket(p, p.buckets[0], st, n_sweeps, s);
+    } else {
+        e = hipEventRecord(p.ev_fork, s);
+        for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i) {
+            e = hipStreamWaitEvent(p.side[i], p.ev_fork, 0);
+            if (e == hipSuccess) e = launch_bucket(p, p.buckets[i], st, n_sweeps, p.side[i]);
+            if (e == hipSuccess) e = hipEventRecord(p.ev_join[i], p.side[i]);
+        }
+        for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, p.ev_join[i], 0);
+    }
     if (e != hipSuccess) return e;
     if (n_sweeps > 0) {
         advance_t_kernel<<<1, 64, 0, s>>>(st.t, n_sweeps);
         e = hipGetLastError();
     }
     return e;
-}
-
-hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
-    if (p.precision == HP_FP64) return launch_sweep_t<double>(p, st, n_sweeps, p.tab.g64, s);
-    return launch_sweep_t<float>(p, st, n_sweeps, p.tab.g32, s);
 }
 
 }  // namespace hp

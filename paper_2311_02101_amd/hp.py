@@ -20,8 +20,8 @@ HP_FP64, HP_FP32, HP_MIXED_BF16 = 0, 1, 2
 PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
 KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
-EXPORTS = ("hp_plan", "hp_run", "hp_check", "hp_plan_query", "hp_free", "hp_status_string",
-           "hp_last_error")
+EXPORTS = ("hp_plan", "hp_run", "hp_tune", "hp_check", "hp_plan_query", "hp_free",
+           "hp_status_string", "hp_last_error")
 
 
 class HpError(RuntimeError):
@@ -44,13 +44,17 @@ class HpRbm(ct.Structure):
 class HpOpts(ct.Structure):
     _fields_ = [("chains", ct.c_int32), ("temp_of_chain", ct.POINTER(ct.c_int32)),
                 ("precision", ct.c_int32), ("alpha", ct.c_double), ("seed", ct.c_uint64),
-                ("threads", ct.c_int32), ("split", ct.c_int32), ("kernel", ct.c_int32)]
+                ("threads", ct.c_int32), ("split", ct.c_int32), ("kernel", ct.c_int32),
+                ("graph", ct.c_int32)]
 
 
 class HpPlanInfo(ct.Structure):
     _fields_ = [("threads", ct.c_int32), ("split", ct.c_int32), ("push_items", ct.c_int32),
-                ("pull_items", ct.c_int32), ("fx_shift", ct.c_int32), ("reserved", ct.c_int32),
-                ("lds_push", ct.c_int64), ("lds_pull", ct.c_int64)]
+                ("pull_items", ct.c_int32), ("fx_shift", ct.c_int32), ("n_buckets", ct.c_int32),
+                ("lds_push", ct.c_int64), ("lds_pull", ct.c_int64),
+                ("bucket_kind", ct.c_int32 * 16), ("bucket_items", ct.c_int32 * 16),
+                ("bucket_threads", ct.c_int32 * 16), ("bucket_max_n", ct.c_int32 * 16),
+                ("bucket_grid", ct.c_int32 * 16)]
 
 
 class HpState(ct.Structure):
@@ -81,6 +85,8 @@ def load():
     lib.hp_plan.restype = ct.c_int
     lib.hp_run.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
     lib.hp_run.restype = ct.c_int
+    lib.hp_tune.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
+    lib.hp_tune.restype = ct.c_int
     lib.hp_plan_query.argtypes = [ct.c_void_p, ct.POINTER(HpPlanInfo)]
     lib.hp_plan_query.restype = ct.c_int
     lib.hp_check.argtypes = [ct.c_void_p]
@@ -125,7 +131,8 @@ class Plan:
     n_vars: list of N_f.  W: [T][K][L], b: [T][L] canonical OR-gate RBMs."""
 
     def __init__(self, tables, n_vars, W, b, *, chains, temps=None, precision="f64",
-                 alpha=1e-3, seed=0, threads=0, split=0, kernel="auto", stream=None):
+                 alpha=1e-3, seed=0, threads=0, split=0, kernel="auto", graph=False,
+                 stream=None):
         lib = load()
         tables = [np.asarray(t, dtype=np.int32) for t in tables]
         n_vars = [int(n) for n in n_vars]
@@ -152,7 +159,7 @@ class Plan:
                 raise ValueError("temps must have one entry per chain")
             tp = _ptr(self.temps, ct.c_int32)
         opts = HpOpts(self.B, tp, PRECISION[precision], float(alpha), int(seed) & (2 ** 64 - 1),
-                      int(threads), int(split), KERNEL[kernel])
+                      int(threads), int(split), KERNEL[kernel], int(bool(graph)))
         h = ct.c_void_p()
         _check(lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts),
                            _stream_handle(stream)))
@@ -162,7 +169,19 @@ class Plan:
         """Launch configuration chosen by the library (dict)."""
         out = HpPlanInfo()
         _check(load().hp_plan_query(self._h, ct.byref(out)))
-        return {f: getattr(out, f) for f, _ in HpPlanInfo._fields_ if f != "reserved"}
+        d = {}
+        nb = min(out.n_buckets, 16)
+        for f, _ in HpPlanInfo._fields_:
+            v = getattr(out, f)
+            d[f] = list(v)[:nb] if f.startswith("bucket_") else v
+        return d
+
+    def tune(self, n_sweeps=5, stream=None):
+        """Autotune the workgroup size of every launch on a scratch state."""
+        scratch = self.new_state([np.zeros((self.B, n), np.uint8) for n in self.n_vars])
+        _check(load().hp_tune(self._h, ct.byref(scratch.c_struct()), int(n_sweeps),
+                              _stream_handle(stream)))
+        return self.info()
 
     @property
     def split(self):

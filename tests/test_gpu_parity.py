@@ -331,3 +331,89 @@ def test_split_against_oracle(hip):
     w = wl.config_workload("plain_n4096_b64")
     _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 64, 30, "f64", w.seed,
                 chains=[0, 33, 63], label="n4096 fp64 auto split")
+
+
+# --------------------------------------------------------------------------
+# Uneven batches: size-class launches, tables in global memory for the
+# largest formulas, persistent grids, hipGraph replay, autotuning
+# --------------------------------------------------------------------------
+def test_wide_tables_variant_against_oracle(hip):
+    from paper_2311_02101_amd import hp
+    sizes = [15000, 16384, 700]
+    tables = [wl.random_formula(n, 9, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    plan = hp.Plan(tables, sizes, W, b, chains=2, precision="f64", seed=9)
+    info = plan.info()
+    say(f"[wide] buckets {info['bucket_kind']} max_n {info['bucket_max_n']}")
+    assert 1 in info["bucket_kind"] and info["pull_items"] == 0
+    plan.free()
+    _trajectory(hip, tables, sizes, W, b, 2, 4, "f64", 9, label="wide tables")
+
+
+def test_persistent_grid_matches_small_batch(hip):
+    from paper_2311_02101_amd import hp
+    n_f = 300
+    sizes = [64 + 3 * (f % 7) for f in range(n_f)]
+    tables = [wl.random_formula(n, 12, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    big = hp.Plan(tables, sizes, W, b, chains=64, precision="f64", seed=12)
+    info = big.info()
+    say(f"[persistent] buckets grid {info['bucket_grid']} items {info['bucket_items']}")
+    assert any(g > 0 for g in info["bucket_grid"])
+    st = big.new_state([wl.initial_state(64, n, 12, tag=f) for f, n in enumerate(sizes)])
+    big.run(st, 15)
+    big.check()
+    small = hp.Plan(tables[:4], sizes[:4], W, b, chains=64, precision="f64", seed=12)
+    st2 = small.new_state([wl.initial_state(64, n, 12, tag=f) for f, n in enumerate(sizes[:4])])
+    small.run(st2, 15)
+    small.check()
+    # the fixed-point scale 2^-S is chosen per plan (from its largest slot
+    # count), so nu may differ in the last bits between the two batches;
+    # the sampled values, counts and best assignments may not
+    for f in range(4):
+        (v1, nu1, s1, b1), (v2, nu2, s2, b2) = st.formula(f), st2.formula(f)
+        assert np.array_equal(v1, v2) and np.array_equal(s1, s2) and np.array_equal(b1, b2)
+        assert np.max(np.abs(nu1 - nu2) / nu2) < 1e-12
+
+
+def test_graph_replays_match_eager(hip):
+    import torch
+    from paper_2311_02101_amd import hp
+    sizes = [300, 5000, 90, 1200]
+    tables = [wl.random_formula(n, 14, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    v0 = [wl.initial_state(8, n, 14, tag=f) for f, n in enumerate(sizes)]
+    eager = hp.Plan(tables, sizes, W, b, chains=8, precision="f64", seed=14)
+    graph = hp.Plan(tables, sizes, W, b, chains=8, precision="f64", seed=14, graph=True)
+    se, sg = eager.new_state(v0), graph.new_state(v0)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rep in range(4):
+        say(f"[graph] replay {rep}")
+        eager.run(se, 7)
+        graph.run(sg, 7)
+        junk.add_(1.0)                  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        for f in range(len(sizes)):
+            for x, y in zip(se.formula(f), sg.formula(f)):
+                assert np.array_equal(x, y), (rep, f)
+        assert se.get_t() == sg.get_t() == 7 * (rep + 1)
+    graph.check()
+
+
+def test_tuned_plan_reproduces_untuned_results(hip):
+    from paper_2311_02101_amd import hp
+    sizes = [128, 2000, 9000]
+    tables = [wl.random_formula(n, 15, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    v0 = [wl.initial_state(4, n, 15, tag=f) for f, n in enumerate(sizes)]
+    ref = hp.Plan(tables, sizes, W, b, chains=4, precision="f32", seed=15)
+    tuned = hp.Plan(tables, sizes, W, b, chains=4, precision="f32", seed=15)
+    info = tuned.tune(n_sweeps=2)
+    say(f"[tune] threads per bucket {info['bucket_threads']}")
+    a, c = ref.new_state(v0), tuned.new_state(v0)
+    ref.run(a, 10)
+    tuned.run(c, 10)
+    _sync()
+    for f in range(len(sizes)):
+        for x, y in zip(a.formula(f), c.formula(f)):
+            assert np.array_equal(x, y)
