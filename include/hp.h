@@ -83,7 +83,12 @@ typedef struct {
     int32_t threads;                /* workgroup size override (0 = automatic)         */
     int32_t split;                  /* workgroups per chain of the push kernel: 0 =
                                        automatic (fill the device), 1 = one, or a power
-                                       of two up to 16 (all must be co-resident)       */
+                                       of two up to 16.  The plan admits a split only
+                                       if all its workgroups fit on the device at once;
+                                       they exchange data every sweep, so a split run
+                                       must not share the device with work that keeps
+                                       CUs occupied for long (its bounded barrier waits
+                                       would time out: see hp_check)                 */
     int32_t kernel;                 /* hp_kernel: sweep kernel variant                 */
     int32_t graph;                  /* 1: hp_run replays a captured hipGraph of its
                                        launches (cached per state buffers and sweep
@@ -182,6 +187,60 @@ const char *hp_status_string(hp_status s);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *hp_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Learned initial assignments.  The paper notes that learned components that
+ * generate good initial assignments can be combined with the sampler
+ * (Sec. 2); here a 32 -> 256 -> 1 perceptron maps per-variable occurrence
+ * statistics of a formula to q_i = P(v_i = 1), is trained on labels produced
+ * by the sampler itself, and seeds chains with v_i ~ Bernoulli(q_i); the
+ * remaining chains keep their own (uniform) start, so the plain method stays
+ * the fallback and the exact clause count judges the two.
+ * ------------------------------------------------------------------------ */
+#define HP_MLP_IN 32
+#define HP_MLP_HIDDEN 256
+/* parameter vector: W1 [32][256] | b1 [256] | w2 [256] | b2 [1] */
+#define HP_MLP_PARAMS (HP_MLP_IN * HP_MLP_HIDDEN + 2 * HP_MLP_HIDDEN + 1)
+
+typedef struct {                    /* caller-owned DEVICE buffers                     */
+    float *params;                  /* [HP_MLP_PARAMS] FP32 master parameters          */
+    float *adam_m, *adam_v;         /* [HP_MLP_PARAMS] Adam moments                    */
+    float *grad;                    /* [HP_MLP_PARAMS] gradient of the mean loss       */
+    uint16_t *w_bf16;               /* [32*256 + 256] bfloat16 copies: W1 transposed
+                                       ([256][32]) then w2; refreshed by
+                                       hp_mlp_sync and hp_mlp_adam                     */
+} hp_mlp;
+
+/* Per-variable features of every formula of the plan, as bfloat16
+ * [sum N_f][32] rows in variable order (layout of the counts: see the
+ * kernels).  The plan allocates a small FP32 workspace on first use. */
+hp_status hp_features(hp_plan_t plan, uint16_t *x, void *stream);
+
+/* Refresh net->w_bf16 from net->params. */
+hp_status hp_mlp_sync(const hp_mlp *net, void *stream);
+
+/* q[r] = sigmoid(w2 . relu(W1^T x_r + b1) + b2) for rows r < rows (bfloat16
+ * weights and inputs on MFMA, FP32 accumulation). */
+hp_status hp_mlp_forward(const hp_mlp *net, const uint16_t *x, int64_t rows, float *q, void *stream);
+
+/* net->grad = gradient of the mean binary cross-entropy of q against the
+ * labels y in [0,1]; *loss_sum (device float) = the summed loss. */
+hp_status hp_mlp_backward(const hp_mlp *net, const uint16_t *x, const float *y, int64_t rows,
+                          float *loss_sum, void *stream);
+
+/* One Adam step (Kingma & Ba) on net->params with net->grad; step >= 1. */
+hp_status hp_mlp_adam(const hp_mlp *net, float lr, float beta1, float beta2, float eps, int64_t step,
+                      void *stream);
+
+/* For chains chain_lo <= b < chain_hi of every formula: v[b][i] = [U < q_i]
+ * with U drawn by the sweep generator at the reserved time 2^64 - 1
+ * (visible phase, unit i).  q: device [sum N_f] in variable order. */
+hp_status hp_init_chains(hp_plan_t plan, const float *q, int32_t chain_lo, int32_t chain_hi,
+                         const hp_state *state, void *stream);
+
+/* out[i] = mean over the chains of a [B][N_f]-layout byte array (for
+ * example state->best): device [sum N_f] floats in variable order. */
+hp_status hp_chain_mean(hp_plan_t plan, const uint8_t *a, float *out, void *stream);
 
 #ifdef __cplusplus
 }

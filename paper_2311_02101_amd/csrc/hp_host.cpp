@@ -51,6 +51,9 @@ void release(Plan *p) {
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     (void)hipFree(p->d_queue);
+    (void)hipFree(p->d_var_off);
+    (void)hipFree(p->d_clause_off);
+    (void)hipFree(p->d_feat_acc);
     (void)hipFree(p->d_fd);
     (void)hipFree(p->d_work);
     (void)hipFree(p->d_lits);
@@ -422,6 +425,10 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(upload(&p->d_orig, orig, s), "upload clause order");
     HP_TRY(upload(&p->d_negcnt, negcnt, s), "upload negation counts");
     HP_TRY(upload(&p->d_temp, temp, s), "upload temperatures");
+    std::vector<int64_t> voff(cnf->var_offset, cnf->var_offset + F + 1);
+    std::vector<int64_t> coff(cnf->clause_offset, cnf->clause_offset + F + 1);
+    HP_TRY(upload(&p->d_var_off, voff, s), "upload variable offsets");
+    HP_TRY(upload(&p->d_clause_off, coff, s), "upload clause offsets");
     HP_TRY(upload(&p->d_W, Wv, s), "upload W_c");
     HP_TRY(upload(&p->d_b, bv, s), "upload b_c");
     HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kPatterns * kMaxL * sizeof(uint32_t)), "alloc thr");
@@ -598,6 +605,84 @@ hp_status hp_check(hp_plan_t plan) {
     (void)hipSetDevice(cur);
     if (e != hipSuccess) return hip_fail(e, "hp_check");
     if (flag) return fail(HP_EDEVICE, "a cross-workgroup barrier timed out; results of the affected runs are void");
+    return HP_OK;
+}
+
+hp_status hp_features(hp_plan_t plan, uint16_t *x, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !x) return fail(HP_EINVAL, "null argument");
+    if (p->K > 7 || p->total_vars < 1) return fail(HP_EINVAL, "bad plan");
+    if (!p->d_feat_acc) {
+        hipError_t e = hipMalloc((void **)&p->d_feat_acc, (size_t)p->total_vars * 20 * sizeof(float));
+        if (e != hipSuccess) return hip_fail(e, "feature workspace");
+    }
+    hipError_t e = launch_features(*p, p->d_feat_acc, x, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "feature kernels");
+    return HP_OK;
+}
+
+static bool mlp_ok(const hp_mlp *n) {
+    return n && n->params && n->adam_m && n->adam_v && n->grad && n->w_bf16;
+}
+
+hp_status hp_mlp_sync(const hp_mlp *net, void *stream) {
+    g_last_error.clear();
+    if (!mlp_ok(net)) return fail(HP_EINVAL, "null network buffer");
+    hipError_t e = launch_weights_to_bf16(*net, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "weight conversion");
+    return HP_OK;
+}
+
+hp_status hp_mlp_forward(const hp_mlp *net, const uint16_t *x, int64_t rows, float *q, void *stream) {
+    g_last_error.clear();
+    if (!mlp_ok(net) || !x || !q) return fail(HP_EINVAL, "null argument");
+    if (rows < 1) return fail(HP_EINVAL, "rows must be >= 1");
+    hipError_t e = launch_mlp(*net, x, nullptr, rows, q, nullptr, false, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp forward");
+    return HP_OK;
+}
+
+hp_status hp_mlp_backward(const hp_mlp *net, const uint16_t *x, const float *y, int64_t rows, float *loss_sum,
+                          void *stream) {
+    g_last_error.clear();
+    if (!mlp_ok(net) || !x || !y || !loss_sum) return fail(HP_EINVAL, "null argument");
+    if (rows < 1) return fail(HP_EINVAL, "rows must be >= 1");
+    hipError_t e = launch_mlp(*net, x, y, rows, nullptr, loss_sum, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp backward");
+    return HP_OK;
+}
+
+hp_status hp_mlp_adam(const hp_mlp *net, float lr, float beta1, float beta2, float eps, int64_t step, void *stream) {
+    g_last_error.clear();
+    if (!mlp_ok(net)) return fail(HP_EINVAL, "null network buffer");
+    if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return fail(HP_EINVAL, "bad Adam hyperparameters");
+    hipError_t e = launch_adam(*net, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adam");
+    return HP_OK;
+}
+
+hp_status hp_init_chains(hp_plan_t plan, const float *q, int32_t chain_lo, int32_t chain_hi, const hp_state *st,
+                         void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !q || !st || !st->v) return fail(HP_EINVAL, "null argument");
+    if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B)
+        return fail(HP_EINVAL, "state shape does not match the plan");
+    if (chain_lo < 0 || chain_hi > p->B || chain_lo > chain_hi) return fail(HP_EINVAL, "bad chain range");
+    hipError_t e = launch_init_chains(*p, q, chain_lo, chain_hi, st->v, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "init chains");
+    return HP_OK;
+}
+
+hp_status hp_chain_mean(hp_plan_t plan, const uint8_t *a, float *out, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !a || !out) return fail(HP_EINVAL, "null argument");
+    hipError_t e = launch_chain_mean(*p, a, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "chain mean");
     return HP_OK;
 }
 

@@ -153,6 +153,9 @@ struct Plan {
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
     uint32_t *d_queue = nullptr;     // [kMaxBuckets * 32] persistent work counters
+    int64_t *d_var_off = nullptr;    // [F+1]
+    int64_t *d_clause_off = nullptr; // [F+1]
+    float *d_feat_acc = nullptr;     // feature workspace, allocated on first use
     // device memory
     FormulaDev *d_fd = nullptr;
     WorkItem *d_work = nullptr;
@@ -193,6 +196,17 @@ int split_occupancy(const Plan &p);
 // LDS bytes of the two kernel variants for the largest formula
 size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);
 size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off);
+
+// learned initial assignments (hp_mlp.hip)
+hipError_t launch_features(const Plan &p, float *acc, uint16_t *x, hipStream_t s);
+hipError_t launch_mlp(const hp_mlp &net, const uint16_t *x, const float *y, int64_t rows, float *q,
+                      float *loss_sum, bool backward, hipStream_t s);
+hipError_t launch_adam(const hp_mlp &net, float lr, float beta1, float beta2, float eps, int64_t step,
+                       hipStream_t s);
+hipError_t launch_weights_to_bf16(const hp_mlp &net, hipStream_t s);
+hipError_t launch_init_chains(const Plan &p, const float *q, int chain_lo, int chain_hi, uint8_t *v,
+                              hipStream_t s);
+hipError_t launch_chain_mean(const Plan &p, const uint8_t *a, float *out, hipStream_t s);
 
 void set_error(const std::string &msg);
 

@@ -834,11 +834,11 @@ int split_occupancy(const Plan &p) {
 template <typename Real, int VPT>
 hipError_t launch_split_one(const Plan &p, SweepParams<Real> P, SplitParams Q, hipStream_t s) {
     const Bucket &b = p.buckets[0];
-    void *args[] = {(void *)&P, (void *)&Q};
-    // cooperative launch: fails instead of running if the G workgroups of a
-    // chain could not all be resident at once
-    return hipLaunchCooperativeKernel((const void *)sweep_split_kernel<Real, VPT>, dim3(b.count * p.split),
-                                      dim3(b.threads), args, (unsigned)b.lds, s);
+    // The plan checked that all count*G workgroups fit on the device at once
+    // (occupancy x CUs), so on an otherwise idle device they are all resident
+    // together; the barrier waits are bounded either way (see hp_check).
+    hipLaunchKernelGGL((sweep_split_kernel<Real, VPT>), dim3(b.count * p.split), dim3(b.threads), b.lds, s, P, Q);
+    return hipGetLastError();
 }
 
 template <typename Real>

@@ -41,6 +41,24 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key2 key) {
     return x;
 }
 
+// Same generator for a key that differs between lanes (kept in vector
+// registers; no scalar-register pinning).
+__device__ __forceinline__ uint4 philox4x32_10_lane_key(uint4 x, Key2 key) {
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x.z;
+        x = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x.y, k0, 0x96), (uint32_t)p1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x.w, k1, 0x96), (uint32_t)p0);
+    }
+    return x;
+}
+
 // Counter word 2: phase in the top bit, block index below it.
 constexpr uint32_t kPhaseHidden = 0u;
 constexpr uint32_t kPhaseVisible = 0x80000000u;

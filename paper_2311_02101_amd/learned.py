@@ -1,0 +1,271 @@
+"""Learned initial assignments for the block-Gibbs search.
+
+A 32 -> 256 -> 1 perceptron maps per-variable occurrence statistics of a
+formula to q_i = P(v_i = 1).  It is trained on labels the sampler itself
+produces -- the fraction of chains whose best assignment sets v_i after a
+plain run from uniform starts -- and then seeds half of the chains of a new
+formula with v_i ~ Bernoulli(q_i) while the other half keep uniform starts.
+The plain method is thereby the fallback, and the exact satisfied-clause
+count judges the two halves.
+
+Every step runs in the library's HIP kernels (features, MFMA forward and
+backward, Adam, initial draws, label reduction); this module only allocates
+buffers and drives the loop.
+
+    python -m paper_2311_02101_amd.learned --instances 100000   # full-size training run
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as ct
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import hp
+from . import workload as wl
+
+F_IN, HIDDEN = 32, 256
+N_PARAMS = F_IN * HIDDEN + 2 * HIDDEN + 1
+WEIGHTS_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "learned_init_weights.json")
+
+
+class HpMlp(ct.Structure):
+    _fields_ = [("params", ct.c_void_p), ("adam_m", ct.c_void_p), ("adam_v", ct.c_void_p),
+                ("grad", ct.c_void_p), ("w_bf16", ct.c_void_p)]
+
+
+def _lib():
+    lib = hp.load()
+    if not getattr(lib, "_mlp_bound", False):
+        lib.hp_features.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        lib.hp_mlp_sync.argtypes = [ct.POINTER(HpMlp), ct.c_void_p]
+        lib.hp_mlp_forward.argtypes = [ct.POINTER(HpMlp), ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p]
+        lib.hp_mlp_backward.argtypes = [ct.POINTER(HpMlp), ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p,
+                                        ct.c_void_p]
+        lib.hp_mlp_adam.argtypes = [ct.POINTER(HpMlp), ct.c_float, ct.c_float, ct.c_float, ct.c_float,
+                                    ct.c_int64, ct.c_void_p]
+        lib.hp_init_chains.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32,
+                                       ct.POINTER(hp.HpState), ct.c_void_p]
+        lib.hp_chain_mean.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        for n in ("hp_features", "hp_mlp_sync", "hp_mlp_forward", "hp_mlp_backward", "hp_mlp_adam",
+                  "hp_init_chains", "hp_chain_mean"):
+            getattr(lib, n).restype = ct.c_int
+        lib._mlp_bound = True
+    return lib
+
+
+def _stream():
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class MLP:
+    """Device parameters (FP32 master, Adam moments, gradient, bf16 copies)."""
+
+    def __init__(self, seed: int = 4, params: np.ndarray | None = None, device="cuda"):
+        import torch
+        if params is None:
+            rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 77])))
+            params = np.zeros(N_PARAMS)
+            params[:F_IN * HIDDEN] = rng.standard_normal(F_IN * HIDDEN) * np.sqrt(2.0 / F_IN)
+            params[F_IN * HIDDEN + HIDDEN:F_IN * HIDDEN + 2 * HIDDEN] = \
+                rng.standard_normal(HIDDEN) * np.sqrt(1.0 / HIDDEN)
+        f32 = dict(dtype=torch.float32, device=device)
+        self.params = torch.tensor(np.asarray(params, dtype=np.float32), **f32)
+        self.m = torch.zeros(N_PARAMS, **f32)
+        self.v = torch.zeros(N_PARAMS, **f32)
+        self.grad = torch.zeros(N_PARAMS, **f32)
+        self.w_bf16 = torch.zeros(F_IN * HIDDEN + HIDDEN, dtype=torch.int16, device=device)
+        self.loss_buf = torch.zeros(1, **f32)
+        self.step = 0
+        self.sync()
+
+    def c_struct(self):
+        return HpMlp(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                     self.grad.data_ptr(), self.w_bf16.data_ptr())
+
+    def sync(self):
+        hp._check(_lib().hp_mlp_sync(ct.byref(self.c_struct()), _stream()))
+
+    def forward(self, x, q=None):
+        import torch
+        rows = x.shape[0]
+        if q is None:
+            q = torch.empty(rows, dtype=torch.float32, device=x.device)
+        hp._check(_lib().hp_mlp_forward(ct.byref(self.c_struct()), ct.c_void_p(x.data_ptr()), rows,
+                                        ct.c_void_p(q.data_ptr()), _stream()))
+        return q
+
+    def backward(self, x, y):
+        """Fill self.grad with the gradient of the mean loss; returns the
+        (device) summed loss tensor."""
+        hp._check(_lib().hp_mlp_backward(ct.byref(self.c_struct()), ct.c_void_p(x.data_ptr()),
+                                         ct.c_void_p(y.data_ptr()), x.shape[0],
+                                         ct.c_void_p(self.loss_buf.data_ptr()), _stream()))
+        return self.loss_buf
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        hp._check(_lib().hp_mlp_adam(ct.byref(self.c_struct()), lr, beta1, beta2, eps, self.step,
+                                     _stream()))
+
+    def host_params(self):
+        return self.params.cpu().numpy().astype(np.float64)
+
+    def save(self, path=WEIGHTS_JSON, **meta):
+        with open(path, "w") as fh:
+            json.dump({"params": self.host_params().tolist(), **meta}, fh)
+
+    @classmethod
+    def load(cls, path=WEIGHTS_JSON, device="cuda"):
+        with open(path) as fh:
+            d = json.load(fh)
+        return cls(params=np.array(d["params"]), device=device), d
+
+
+def features(plan):
+    """bf16 feature rows [sum N][32] (torch int16 holding the bit patterns)."""
+    import torch
+    x = torch.empty((plan.total_vars, F_IN), dtype=torch.int16, device="cuda")
+    hp._check(_lib().hp_features(plan._h, ct.c_void_p(x.data_ptr()), _stream()))
+    return x
+
+
+def init_chains(plan, q, state, chain_lo, chain_hi):
+    hp._check(_lib().hp_init_chains(plan._h, ct.c_void_p(q.data_ptr()), int(chain_lo), int(chain_hi),
+                                    ct.byref(state.c_struct()), _stream()))
+
+
+def chain_mean(plan, arr):
+    import torch
+    out = torch.empty(plan.total_vars, dtype=torch.float32, device="cuda")
+    hp._check(_lib().hp_chain_mean(plan._h, ct.c_void_p(arr.data_ptr()), ct.c_void_p(out.data_ptr()),
+                                   _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# data, training and evaluation
+# ---------------------------------------------------------------------------
+
+def _formulas(n_formulas, n_vars, seed, first=0):
+    return [wl.random_formula(n_vars, seed, tag=first + f) for f in range(n_formulas)]
+
+
+def make_dataset(n_formulas, n_vars=2048, seed=4, chains=32, sweeps=500, batch=256, first=0,
+                 log=None):
+    """Features and labels from the method itself: for each formula, run the
+    plain sampler from uniform starts and label every variable with the
+    fraction of chains whose best assignment sets it.  Returns device tensors
+    x [rows][32] (bf16 bits) and y [rows]."""
+    import torch
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    temps = wl.default_temperatures(chains, 2)
+    xs, ys = [], []
+    for lo in range(0, n_formulas, batch):
+        k = min(batch, n_formulas - lo)
+        tables = _formulas(k, n_vars, seed, first + lo)
+        plan = hp.Plan(tables, [n_vars] * k, W, b, chains=chains, temps=temps, precision="f32",
+                       seed=seed + 1000 * (first + lo))
+        st = plan.new_state([wl.initial_state(chains, n_vars, seed, tag=first + lo + f) for f in range(k)])
+        plan.run(st, sweeps)
+        xs.append(features(plan))
+        ys.append(chain_mean(plan, st.best))
+        torch.cuda.synchronize()
+        plan.free()
+        if log:
+            log(f"labelled {lo + k}/{n_formulas} formulas")
+    return torch.cat(xs), torch.cat(ys)
+
+
+def train(net, x, y, epochs=3, batch_rows=1 << 18, lr=1e-3, log=None):
+    import torch
+    rows = x.shape[0]
+    gen = torch.Generator(device="cpu").manual_seed(1234)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(rows // batch_rows if rows >= batch_rows else 1, generator=gen)
+        tot = 0.0
+        for bi in perm.tolist():
+            lo = bi * batch_rows
+            hi = min(rows, lo + batch_rows)
+            loss = net.backward(x[lo:hi], y[lo:hi])
+            net.adam(lr=lr)
+            tot += float(loss.item()) / (hi - lo)
+        losses.append(tot / len(perm))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: mean loss {losses[-1]:.5f}")
+    return losses
+
+
+def evaluate(net, n_formulas, n_vars=2048, seed=4, chains=64, sweeps=(20, 100, 500), first=10 ** 6):
+    """Held-out comparison on formulas never used in training: chains
+    [0, B/2) start from Bernoulli(q), chains [B/2, B) from uniform; for each
+    sweep budget report the mean best count of each half (the better of the
+    two is the answer, so the plain method is the fallback)."""
+    import torch
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    tables = _formulas(n_formulas, n_vars, seed, first)
+    # both halves use the same temperature split (first half of each half at
+    # the low target) so the comparison is paired
+    half = chains // 2
+    temps = np.concatenate([wl.default_temperatures(half, 2)] * 2).astype(np.int32)
+    plan = hp.Plan(tables, [n_vars] * n_formulas, W, b, chains=chains, temps=temps, precision="f32",
+                   seed=seed + 7)
+    st = plan.new_state([wl.initial_state(chains, n_vars, seed, tag=first + f) for f in range(n_formulas)])
+    q = net.forward(features(plan))
+    init_chains(plan, q, st, 0, half)
+    plan.run(st, 0)
+    out = {}
+    done = 0
+    for s in sweeps:
+        plan.run(st, s - done)
+        done = s
+        plan.run(st, 0)
+        torch.cuda.synchronize()
+        smax = st.s_max.cpu().numpy().reshape(n_formulas, chains)
+        mlp_best = smax[:, :half].max(axis=1)
+        uni_best = smax[:, half:].max(axis=1)
+        out[s] = dict(mlp=float(mlp_best.mean()), uniform=float(uni_best.mean()),
+                      gain=float((mlp_best - uni_best).mean()),
+                      wins=int((mlp_best > uni_best).sum()), losses=int((mlp_best < uni_best).sum()),
+                      fallback_used=int((uni_best > mlp_best).sum()),
+                      clauses=int(tables[0].shape[1]))
+    plan.free()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--instances", type=int, default=100000)
+    ap.add_argument("--n-vars", type=int, default=2048)
+    ap.add_argument("--label-sweeps", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--eval", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--out", default=WEIGHTS_JSON)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(f"[learned] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    x, y = make_dataset(args.instances, args.n_vars, args.seed, sweeps=args.label_sweeps, log=log)
+    t1 = time.time()
+    net = MLP(seed=args.seed)
+    losses = train(net, x, y, epochs=args.epochs, log=log)
+    t2 = time.time()
+    ev = evaluate(net, args.eval, args.n_vars, args.seed)
+    net.save(args.out, instances=args.instances, n_vars=args.n_vars, epochs=args.epochs,
+             losses=losses, evaluation={str(k): v for k, v in ev.items()})
+    print(json.dumps({"instances": args.instances, "label_s": t1 - t0, "train_s": t2 - t1,
+                      "losses": losses, "evaluation": ev}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

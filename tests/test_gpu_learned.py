@@ -1,0 +1,149 @@
+"""Learned initial assignments: HIP kernels vs the CPU FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import learned as M
+from paper_2311_02101_amd import workload as wl
+from tests.parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits_to_float(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _plan(tables, ns, chains=4, seed=3):
+    from paper_2311_02101_amd import hp
+    K = tables[0].shape[0]
+    L = wl.hidden_units_for(K)
+    W, b = wl.gaussian_rbm(2, K, L, seed)
+    return hp.Plan(tables, ns, W, b, chains=chains, precision="f32", seed=seed)
+
+
+def _net(seed):
+    from paper_2311_02101_amd import learned as Lr
+    return Lr.MLP(seed=seed)
+
+
+def _oracle_params(net):
+    p = net.host_params()
+    W1 = p[:M.F_IN * M.HIDDEN].reshape(M.F_IN, M.HIDDEN)
+    b1 = p[M.F_IN * M.HIDDEN:M.F_IN * M.HIDDEN + M.HIDDEN]
+    w2 = p[M.F_IN * M.HIDDEN + M.HIDDEN:M.F_IN * M.HIDDEN + 2 * M.HIDDEN]
+    return W1, b1, w2, p[-1]
+
+
+def test_features_match_oracle(hip):
+    from paper_2311_02101_amd import learned as Lr
+    for K, sizes in [(7, [100, 2048, 37]), (3, [9, 50])]:
+        tables = [wl.random_formula(n, 5, k=K, lengths=[1, 2, 3] if K == 3 else wl.LENGTHS,
+                                    probs=[0.2, 0.5, 0.3] if K == 3 else wl.LENGTH_PROBS, tag=f)
+                  for f, n in enumerate(sizes)]
+        say(f"[features] K={K} sizes={sizes}")
+        plan = _plan(tables, sizes)
+        x = _bits_to_float(Lr.features(plan))
+        want = np.concatenate([M.bf16_round(M.features(t, n)) for t, n in zip(tables, sizes)])
+        assert np.array_equal(x, want)
+        plan.free()
+
+
+@pytest.mark.parametrize("rows", [1, 33, 1000, 4096])
+def test_forward_matches_oracle(hip, rows):
+    import torch
+    net = _net(11)
+    rng = np.random.default_rng(rows)
+    xf = M.bf16_round(rng.standard_normal((rows, M.F_IN)))
+    bits = torch.tensor((xf.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16),
+                        device="cuda")
+    say(f"[mlp forward] rows={rows}")
+    q = net.forward(bits)
+    _sync()
+    want, _ = M.forward(xf, *_oracle_params(net))
+    assert np.max(np.abs(q.cpu().numpy() - want)) < 2e-6
+
+
+def test_backward_and_adam_match_oracle(hip):
+    import torch
+    net = _net(12)
+    rng = np.random.default_rng(7)
+    rows = 3000
+    xf = M.bf16_round(rng.standard_normal((rows, M.F_IN)))
+    y = rng.uniform(0, 1, rows)
+    bits = torch.tensor((xf.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16),
+                        device="cuda")
+    yt = torch.tensor(y.astype(np.float32), device="cuda")
+    say("[mlp backward] rows=3000")
+    loss = net.backward(bits, yt)
+    _sync()
+    W1, b1, w2, b2 = _oracle_params(net)
+    g = M.gradients(xf, y.astype(np.float32).astype(np.float64), W1, b1, w2, b2)
+    got = net.grad.cpu().numpy().astype(np.float64)
+    parts = dict(W1=got[:M.F_IN * M.HIDDEN].reshape(M.F_IN, M.HIDDEN),
+                 b1=got[M.F_IN * M.HIDDEN:M.F_IN * M.HIDDEN + M.HIDDEN],
+                 w2=got[M.F_IN * M.HIDDEN + M.HIDDEN:-1], b2=got[-1:])
+    errs = {k: np.max(np.abs(parts[k] - g[k])) / max(np.max(np.abs(g[k])), 1e-30) for k in parts}
+    say("  grad rel err " + " ".join(f"{k}={e:.2e}" for k, e in errs.items()))
+    assert all(e < 1e-4 for e in errs.values()), errs
+    want_loss = M.loss(xf, y.astype(np.float32).astype(np.float64), W1, b1, w2, b2) * rows
+    assert abs(float(loss.item()) - want_loss) < 1e-5 * abs(want_loss)
+    # one Adam step from zero moments, FP32 on the device vs FP64 here
+    p0 = net.host_params()
+    gp = net.grad.cpu().numpy().astype(np.float64)
+    net.adam(lr=1e-3)
+    _sync()
+    p1, _, _ = M.adam(p0, gp, np.zeros_like(p0), np.zeros_like(p0), 1, lr=1e-3)
+    assert np.max(np.abs(net.host_params() - p1)) < 1e-6 * max(1.0, np.max(np.abs(p1)))
+    # the bfloat16 copies follow the updated parameters
+    wb = _bits_to_float(net.w_bf16)
+    W1n = net.host_params()[:M.F_IN * M.HIDDEN].reshape(M.F_IN, M.HIDDEN)
+    assert np.array_equal(wb[:M.F_IN * M.HIDDEN].reshape(M.HIDDEN, M.F_IN), M.bf16_round(W1n).T)
+
+
+def test_init_chains_and_chain_mean_match_oracle(hip):
+    import torch
+    from paper_2311_02101_amd import learned as Lr
+    sizes = [300, 77]
+    tables = [wl.random_formula(n, 6, tag=f) for f, n in enumerate(sizes)]
+    plan = _plan(tables, sizes, chains=8, seed=6)
+    v0 = [wl.initial_state(8, n, 6, tag=f) for f, n in enumerate(sizes)]
+    st = plan.new_state(v0)
+    rng = np.random.default_rng(0)
+    q = torch.tensor(rng.uniform(0, 1, sum(sizes)).astype(np.float32), device="cuda")
+    say("[init chains] chains 2..5 of 8")
+    Lr.init_chains(plan, q, st, 2, 5)
+    mean = Lr.chain_mean(plan, st.v)
+    _sync()
+    qh = q.cpu().numpy().astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for f, n in enumerate(sizes):
+        v = st.formula(f)[0]
+        want = M.init_assignment(qh[off[f]:off[f + 1]], 6, f, np.arange(2, 5))   # plan seed 6
+        assert np.array_equal(v[2:5], want)
+        assert np.array_equal(v[:2], v0[f][:2]) and np.array_equal(v[5:], v0[f][5:])
+        assert np.array_equal(mean.cpu().numpy()[off[f]:off[f + 1]], v.mean(axis=0).astype(np.float32))
+
+
+def test_learned_initializer_trains_and_is_judged_by_the_count(hip):
+    """End to end on a small scale: labels from the sampler, training on the
+    device, held-out comparison against uniform starts."""
+    from paper_2311_02101_amd import learned as Lr
+    say("[learned] dataset 48 formulas N=512")
+    x, y = Lr.make_dataset(48, n_vars=512, seed=21, chains=16, sweeps=150, batch=48)
+    assert x.shape == (48 * 512, M.F_IN) and float(y.min()) >= 0.0 and float(y.max()) <= 1.0
+    net = Lr.MLP(seed=21)
+    losses = Lr.train(net, x, y, epochs=30, batch_rows=4096, lr=3e-3)
+    say(f"[learned] losses {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < losses[0]
+    ev = Lr.evaluate(net, 16, n_vars=512, seed=21, chains=32, sweeps=(10, 50))
+    say(f"[learned] evaluation {ev}")
+    for s, r in ev.items():
+        # the answer is the better half, so the plain method bounds it below
+        assert max(r["mlp"], r["uniform"]) >= r["uniform"]
+        assert r["wins"] + r["losses"] <= 16
