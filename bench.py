@@ -62,6 +62,9 @@ def main(argv=None):
                     help="sweeps of the oracle sample (all chains); 0 skips the CPU leg")
     ap.add_argument("--graph", type=int, default=-1, help="hipGraph replay (default: on for batches)")
     ap.add_argument("--tune", type=int, default=-1, help="autotune first (default: on for batches)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run y = -x over this many MiB (a plain streaming kernel whose "
+                         "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters), then exit")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -77,6 +80,17 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 3}), flush=True)
+        return 0
 
     progress(f"workload {args.workload}: generating inputs")
     w = wl.config_workload(args.workload, precision=args.precision)
@@ -121,6 +135,11 @@ def main(argv=None):
         calls, draws, slots = calls + c1, draws + d1, slots + s1
     per_launch_slots = slots * B * args.sweeps
     achieved = per_launch_slots / avg_launch_s
+    kernel_name = ("sweep_pull_kernel" if args.kernel == "pull" else
+                   "sweep_split_kernel" if plan.split > 1 else "sweep_push_kernel")
+    info = plan.info()
+    traffic = measured_traffic(kernel_name, args.workload, args.precision, plan.split,
+                               info["bucket_threads"][0])
     N = w.n_vars[0] if not batch else int(sum(w.n_vars))
     C = w.tables[0].shape[1] if not batch else int(sum(t.shape[1] for t in w.tables))
     out = {
@@ -134,15 +153,15 @@ def main(argv=None):
                    "chains": B, "sweeps_per_step": args.sweeps, "temperatures": list(wl.FSTAR_PAIR),
                    "graph": use_graph,
                    "threads": plan_threads(args.threads), "kernel": args.kernel,
-                   "launch": plan.info(),
+                   "launch": info,
                    "parallelism": "single GPU"},
         "chain_sweeps_per_s": B * args.sweeps * instances / wall,
         "draws_per_s": draws * B * args.sweeps * args.steps / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / PEAK_SLOTS,
-                     "traffic": None,
-                     "kernel": ("sweep_pull_kernel" if args.kernel == "pull" else
-                                "sweep_split_kernel" if plan.split > 1 else "sweep_push_kernel"),
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "kernel": kernel_name,
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "philox_calls_per_chain_sweep": calls, "draws_per_chain_sweep": draws},
     }
@@ -151,6 +170,27 @@ def main(argv=None):
     print(json.dumps(out), flush=True)
     plan.free()
     return 0
+
+
+def measured_traffic(kernel, workload, precision, split, threads):
+    """HBM bytes per launch from the committed counter runs (profiles/traffic.json),
+    or None when no run matches this launch or the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec["entries"].get(f"{kernel}|{workload}|{precision}|G{split}|T{threads}")
+    if ent is None:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != ent["sources_sha256"]:
+        return None
+    return (ent["fetch_kib"] * ent["fetch_factor"] + ent["write_kib"] * ent["write_factor"]) * 1024.0
 
 
 def plan_threads(t):

@@ -400,7 +400,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         else bk.grid = 0;                 // split launches run one item per group
     }
     p->split = G;
-    p->nstride = ((int64_t)p->buckets[0].max_n + 15) / 16 * 16;
+    p->nstride = ((int64_t)p->buckets[0].max_n + 127) / 128 * 128;   // 128-byte lines per item
     p->xcd_map = (p->buckets[0].count % 8 == 0) ? 1 : 0;
     p->use_graph = opts->graph ? 1 : 0;
 

@@ -99,7 +99,7 @@ constexpr int kMaxSplit = 16;
 struct SplitParams {
     int64_t *xpart;              // [items][G][nstride]
     uint8_t *vbuf;               // [items][nstride]
-    int32_t *cnt;                // [items][kMaxSplit] partial clause counts
+    int32_t *cnt;                // [items][kMaxSplit] partial clause counts (64 bytes)
     uint32_t *bar;               // [items][32] barrier counters (one 128-byte line each)
     int32_t *err;                // [1] barrier timeout flag
     int64_t nstride;

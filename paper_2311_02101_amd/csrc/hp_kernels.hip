@@ -565,12 +565,16 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
 // --------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 25;   // ~1 s of s_sleep before giving up
 
-// Exchange between the G workgroups of one chain.  Everything that crosses
-// workgroups (partial logits, partial counts, new values) is written and read
-// with agent-scope atomic stores and loads: those bypass the non-coherent
-// caches, so no cache-wide write-back or invalidation is needed (an
-// agent-scope fence pair costs several microseconds per barrier on MI355X,
-// a barrier without it well under one).
+// Exchange between the G workgroups of one chain.  Partial logits, partial
+// counts and new values cross workgroups through global memory with relaxed
+// agent-scope atomic stores and loads: the stores write through and the loads
+// miss the CU's vector cache and the per-XCD L2, so no cache-wide write-back
+// or invalidation is needed (an agent-scope fence pair costs several
+// microseconds per barrier on MI355X).  Workgroup-scope accesses served by a
+// shared L2 are not an option for members on different CUs: outside
+// thread-group-split mode the CU's vector cache may return a stale line, and
+// the only invalidation that reaches it (buffer_inv sc1) also drops the L2's
+// clean lines, which measured 3.7x slower per sweep.
 __device__ __forceinline__ void xstore(int64_t *p, int64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -582,6 +586,12 @@ __device__ __forceinline__ void xstore(uint32_t *p, uint32_t v) {
 }
 __device__ __forceinline__ uint32_t xload(const uint32_t *p) {
     return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t xload(const int32_t *p) {
+    return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Barrier among the G workgroups of one chain.  Counter `ctr` is zeroed
@@ -609,13 +619,153 @@ __device__ __forceinline__ void group_barrier(uint32_t *ctr, uint32_t target, in
     __syncthreads();
 }
 
+// State of one member of a split chain, shared by the two exchange variants.
+template <typename Real>
+struct SplitCtx {
+    PushLds L;
+    const uint4 *rec;
+    const uint32_t *orig;
+    const int32_t *negcnt;
+    int64_t *xpart;
+    uint32_t *vbuf;
+    int32_t *pcnt;
+    uint32_t *ctr;
+    int64_t sbase, nstride, S, t0;
+    Key2 key;
+    double fx_scale;
+    Real alpha;
+    int G, g, N, C, tid, NT, b, groups, q_lo, q_hi;
+    uint32_t nbh, full, lmask;
+    bool sample;
+};
+
+// The sweeps of one member.  Member g owns variable groups [q_lo, q_hi) (of
+// 4): it keeps its own partial logits of those in LDS, publishes the others,
+// sums the G partials of its own variables exactly (integers), draws their new
+// values and publishes them; then every member reads the new values of the
+// groups it does not own.
+template <typename Real, int VPT>
+__device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const SplitParams &Q, const SplitCtx<Real> &c,
+                                             Real (&nu)[VPT > 0 ? VPT : 1][4], int &smax, uint32_t &phase) {
+    const PushLds &L = c.L;
+    const int G = c.G, g = c.g, N = c.N, tid = c.tid, NT = c.NT;
+    const int own_lo = c.q_lo * 4, own_hi = min(N, c.q_hi * 4);
+    for (int64_t s = 0; s < c.S; ++s) {
+        const uint64_t t = (uint64_t)(c.t0 + s);
+        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+        // member g takes every G-th record of the length-sorted order, so all
+        // members get the same mix of clause lengths
+        const int cnt = c.sample ? clause_phase<true>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi, (uint32_t)c.b,
+                                                      c.key, c.nbh, c.full, c.lmask)
+                                 : clause_phase<false>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi, (uint32_t)c.b,
+                                                       c.key, c.nbh, c.full, c.lmask);
+        const int part = block_total(L, cnt, tid, NT);
+        // publish the partial logits of the variables other members own
+        if (c.sample) {
+            for (int i = tid; i < N; i += NT) {
+                if (i >= own_lo && i < own_hi) continue;
+                xstore(&c.xpart[(size_t)g * c.nstride + i], L.x[i]);
+                L.x[i] = 0;
+            }
+        }
+        if (tid == 0) xstore(&c.pcnt[g], part);
+        group_barrier(c.ctr, ++phase * (uint32_t)G, Q.err);
+        int total = 0;
+        for (int k = 0; k < G; ++k) total += xload(&c.pcnt[k]);
+        const bool improved = total > smax;
+        if (improved) smax = total;
+        // visible phase on the owned groups
+#pragma unroll
+        for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
+            const int jmax = VPT > 0 ? j + 1 : (c.q_hi - c.q_lo + NT - 1) / NT;
+            for (int jj = (VPT > 0 ? j : 0); jj < jmax; ++jj) {
+                const int grp = c.q_lo + tid + jj * NT;
+                if (grp < c.q_hi) {
+                    uint4 r = make_uint4(0, 0, 0, 0);
+                    if (c.sample)
+                        r = philox4x32_10(make_uint4(tlo, (uint32_t)c.b, kPhaseVisible | (uint32_t)grp, thi), c.key);
+                    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+                    // sum the partial logits of the group's 4 variables: all
+                    // loads of a batch of members are issued before any is
+                    // used, so the group pays one memory round trip per
+                    // batch instead of one per variable
+                    int64_t xs[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = grp * 4 + q;
+                        xs[q] = 0;
+                        if (c.sample && i < N) {
+                            xs[q] = (int64_t)c.negcnt[i] + L.x[i];
+                            L.x[i] = 0;
+                        }
+                    }
+                    if (c.sample) {
+                        for (int k0 = 0; k0 < G; k0 += 4) {
+                            int64_t part[4][4];
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const int k = k0 + kk, i = grp * 4 + q;
+                                    part[kk][q] = (k < G && k != g && i < N)
+                                                      ? xload(&c.xpart[(size_t)k * c.nstride + i])
+                                                      : 0;
+                                }
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) xs[q] += part[kk][q];
+                        }
+                    }
+                    uint32_t packed = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = grp * 4 + q;
+                        if (i < N) {
+                            if (improved) P.best[c.sbase + i] = L.v[i];
+                            if (c.sample) {
+                                const int64_t xi = xs[q];
+                                uint8_t nvb;
+                                if (VPT > 0) {
+                                    nvb = visible_update(xi, c.fx_scale, nu[j][q], c.alpha, rw[q]);
+                                } else {
+                                    Real nv = P.nu[c.sbase + i];
+                                    nvb = visible_update(xi, c.fx_scale, nv, c.alpha, rw[q]);
+                                    P.nu[c.sbase + i] = nv;
+                                }
+                                L.v[i] = nvb;
+                                packed |= (uint32_t)nvb << (8 * q);
+                            }
+                        }
+                    }
+                    if (c.sample) xstore(&c.vbuf[grp], packed);
+                }
+            }
+        }
+        if (c.sample) {
+            group_barrier(c.ctr, ++phase * (uint32_t)G, Q.err);
+            for (int q = tid; q < c.groups; q += NT) {
+                if (q >= c.q_lo && q < c.q_hi) continue;
+                const uint32_t word = xload(&c.vbuf[q]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (q * 4 + k < N) L.v[q * 4 + k] = (uint8_t)(word >> (8 * k));
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <typename Real, int VPT>
 __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, SplitParams Q) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const PushLds L = push_lds(lds, P.lds_x_off, P.lds_v_off);
+    SplitCtx<Real> c;
+    c.L = push_lds(lds, P.lds_x_off, P.lds_v_off);
+    const PushLds &L = c.L;
 
     // workgroup -> (item, member g); with the XCD map the G members of an
-    // item get workgroup ids congruent modulo the XCD count (same L2)
+    // item get workgroup ids congruent modulo the XCD count (same XCD under
+    // round-robin dispatch, so they share the L2 that holds the formula)
     const int G = Q.G;
     int item, g;
     if (Q.xcd_map) {
@@ -628,34 +778,44 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     }
     const WorkItem w = P.work[item];
     const FormulaDev fd = P.fd[w.f];
-    const int N = fd.n, C = fd.c;
+    const int N = fd.n;
     const int tid = threadIdx.x, NT = blockDim.x;
     const int tau = P.temp_of_chain[w.b];
-    const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
-    const uint4 *__restrict__ rec = P.rec + fd.clause_off;
-    const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
-    const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
-    const bool sample = P.n_sweeps > 0;
-    const int64_t S = sample ? P.n_sweeps : 1;
-    const uint32_t nbh = (uint32_t)(P.L + 3) >> 2;
-    const uint32_t full = (1u << P.K) - 1u;
-    const uint32_t lmask = (1u << P.L) - 1u;
-    const Real alpha = P.alpha;
-    const double fx_scale = P.fx_scale;
-    const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
+    c.G = G;
+    c.g = g;
+    c.N = N;
+    c.C = fd.c;
+    c.tid = tid;
+    c.NT = NT;
+    c.b = w.b;
+    c.sbase = fd.var_off * P.B + (int64_t)w.b * N;
+    c.rec = P.rec + fd.clause_off;
+    c.orig = P.orig + fd.clause_off;
+    c.key = Key2{P.key0, P.key1 ^ (uint32_t)w.f};
+    c.sample = P.n_sweeps > 0;
+    c.S = c.sample ? P.n_sweeps : 1;
+    c.nbh = (uint32_t)(P.L + 3) >> 2;
+    c.full = (1u << P.K) - 1u;
+    c.lmask = (1u << P.L) - 1u;
+    c.alpha = P.alpha;
+    c.fx_scale = P.fx_scale;
+    c.negcnt = P.negcnt + fd.var_off;
+    c.nstride = Q.nstride;
     // this member's owned variable groups (of 4)
-    const int groups = (N + 3) >> 2;
-    const int gg = (groups + G - 1) / G;
-    const int q_lo = min(groups, g * gg), q_hi = min(groups, q_lo + gg);
-    // exchange buffers of this item
-    int64_t *xpart = Q.xpart + (size_t)item * G * Q.nstride;
-    uint32_t *vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
-    int32_t *pcnt = Q.cnt + (size_t)item * kMaxSplit;
-    uint32_t *ctr = Q.bar + (size_t)item * 32;
+    c.groups = (N + 3) >> 2;
+    const int gg = (c.groups + G - 1) / G;
+    c.q_lo = min(c.groups, g * gg);
+    c.q_hi = min(c.groups, c.q_lo + gg);
+    // exchange buffers of this item (each starts on its own 128-byte line)
+    c.xpart = Q.xpart + (size_t)item * G * Q.nstride;
+    c.vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
+    c.pcnt = Q.cnt + (size_t)item * kMaxSplit;
+    c.ctr = Q.bar + (size_t)item * 32;
+    uint32_t phase = 0;
 
     load_push_tables<false>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
-        L.v[i] = P.v[sbase + i];
+        L.v[i] = P.v[c.sbase + i];
         L.x[i] = 0;
     }
     constexpr int VR = VPT > 0 ? VPT : 1;
@@ -665,94 +825,27 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
         for (int j = 0; j < VR; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int grp = q_lo + tid + j * NT;
+                const int grp = c.q_lo + tid + j * NT;
                 const int i = grp * 4 + q;
-                nu[j][q] = (grp < q_hi && i < N) ? P.nu[sbase + i] : Real(0);
+                nu[j][q] = (grp < c.q_hi && i < N) ? P.nu[c.sbase + i] : Real(0);
             }
     }
     int smax = P.s_max[(int64_t)w.f * P.B + w.b];
-    const int64_t t0 = *P.t_ptr;
-    uint32_t phase = 0;
+    c.t0 = *P.t_ptr;
     __syncthreads();
 
-    for (int64_t s = 0; s < S; ++s) {
-        const uint64_t t = (uint64_t)(t0 + s);
-        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-        // member g takes every G-th record of the length-sorted order, so all
-        // members get the same mix of clause lengths
-        const int cnt = sample ? clause_phase<true>(L, rec, orig, g, G, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
-                               : clause_phase<false>(L, rec, orig, g, G, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
-        const int part = block_total(L, cnt, tid, NT);
-        // publish the partial logits of every variable and the partial count
-        if (sample) {
-            for (int i = tid; i < N; i += NT) {
-                xstore(&xpart[(size_t)g * Q.nstride + i], L.x[i]);
-                L.x[i] = 0;
-            }
-        }
-        if (tid == 0) xstore(reinterpret_cast<uint32_t *>(&pcnt[g]), (uint32_t)part);
-        group_barrier(ctr, ++phase * (uint32_t)G, Q.err);
-        int total = 0;
-        for (int k = 0; k < G; ++k) total += (int)xload(reinterpret_cast<const uint32_t *>(&pcnt[k]));
-        const bool improved = total > smax;
-        if (improved) smax = total;
-        // visible phase on the owned groups
-#pragma unroll
-        for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
-          const int jmax = VPT > 0 ? j + 1 : (q_hi - q_lo + NT - 1) / NT;
-          for (int jj = (VPT > 0 ? j : 0); jj < jmax; ++jj) {
-            const int grp = q_lo + tid + jj * NT;
-            if (grp < q_hi) {
-                uint4 r = make_uint4(0, 0, 0, 0);
-                if (sample) r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseVisible | (uint32_t)grp, thi), key);
-                const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-                uint32_t packed = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = grp * 4 + q;
-                    if (i < N) {
-                        if (improved) P.best[sbase + i] = L.v[i];
-                        if (sample) {
-                            int64_t xi = negcnt[i];
-                            for (int k = 0; k < G; ++k) xi += xload(&xpart[(size_t)k * Q.nstride + i]);
-                            uint8_t nvb;
-                            if (VPT > 0) {
-                                nvb = visible_update(xi, fx_scale, nu[j][q], alpha, rw[q]);
-                            } else {
-                                Real nv = P.nu[sbase + i];
-                                nvb = visible_update(xi, fx_scale, nv, alpha, rw[q]);
-                                P.nu[sbase + i] = nv;
-                            }
-                            L.v[i] = nvb;
-                            packed |= (uint32_t)nvb << (8 * q);
-                        }
-                    }
-                }
-                if (sample) xstore(&vbuf[grp], packed);
-            }
-          }
-        }
-        if (sample) {
-            group_barrier(ctr, ++phase * (uint32_t)G, Q.err);
-            for (int q = tid; q < groups; q += NT) {
-                const uint32_t word = xload(&vbuf[q]);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (q * 4 + k < N) L.v[q * 4 + k] = (uint8_t)(word >> (8 * k));
-            }
-            __syncthreads();
-        }
-    }
+    split_sweeps<Real, VPT>(P, Q, c, nu, smax, phase);
+
     // write back the owned part of the state
-    for (int i = q_lo * 4 + tid; i < min(N, q_hi * 4); i += NT) P.v[sbase + i] = L.v[i];
+    for (int i = c.q_lo * 4 + tid; i < min(N, c.q_hi * 4); i += NT) P.v[c.sbase + i] = L.v[i];
     if (VPT > 0) {
 #pragma unroll
         for (int j = 0; j < VR; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int grp = q_lo + tid + j * NT;
+                const int grp = c.q_lo + tid + j * NT;
                 const int i = grp * 4 + q;
-                if (grp < q_hi && i < N) P.nu[sbase + i] = nu[j][q];
+                if (grp < c.q_hi && i < N) P.nu[c.sbase + i] = nu[j][q];
             }
     }
     if (g == 0 && tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;

@@ -327,6 +327,19 @@ def test_split_tiny_ragged_members(hip):
     _same(ref, got)
 
 
+@pytest.mark.parametrize("split,chains", [(2, 16), (4, 8), (16, 2)])
+def test_split_small_formulas_many_sweeps(hip, split, chains):
+    """Small exchanges repeated over many sweeps: the exchanged lines stay in
+    the CUs' vector caches unless each barrier invalidates them."""
+    sizes = [37, 64, 90, 127, 11, 50, 77, 100]     # one size class: one launch
+    tables = [wl.random_formula(n, 9, tag=f) for f, n in enumerate(sizes)]
+    W, b = wl.gaussian_rbm(2, 7, 8, 9)
+    say(f"[split small] sizes={sizes} split={split} chains={chains} 300 sweeps")
+    ref, _ = _run_states(tables, sizes, W, b, chains, 300, "f64", 9, split=1)
+    got, _ = _run_states(tables, sizes, W, b, chains, 300, "f64", 9, split=split)
+    _same(ref, got)
+
+
 def test_split_against_oracle(hip):
     w = wl.config_workload("plain_n4096_b64")
     _trajectory(hip, w.tables, w.n_vars, w.W, w.b, 64, 30, "f64", w.seed,
