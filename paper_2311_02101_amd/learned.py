@@ -156,19 +156,55 @@ def _formulas(n_formulas, n_vars, seed, first=0):
     return [wl.random_formula(n_vars, seed, tag=first + f) for f in range(n_formulas)]
 
 
+def _formula_task(args):
+    n_vars, seed, tag = args
+    return wl.random_formula(n_vars, seed, tag=tag)
+
+
+class FormulaPool:
+    """Host worker processes that generate formulas (NumPy only, never the
+    GPU).  Create it before the process first uses the GPU: the workers are
+    forked."""
+
+    def __init__(self, workers):
+        import multiprocessing as mp
+        self.pool = mp.get_context("fork").Pool(workers) if workers > 1 else None
+
+    def submit(self, n_formulas, n_vars, seed, first):
+        tasks = [(n_vars, seed, first + f) for f in range(n_formulas)]
+        if self.pool is None:
+            res = [_formula_task(t) for t in tasks]
+            return lambda: res
+        handle = self.pool.map_async(_formula_task, tasks, chunksize=8)
+        return lambda: handle.get()
+
+    def close(self):
+        if self.pool is not None:
+            self.pool.close()
+            self.pool.join()
+
+
 def make_dataset(n_formulas, n_vars=2048, seed=4, chains=32, sweeps=500, batch=256, first=0,
-                 log=None):
+                 log=None, pool=None):
     """Features and labels from the method itself: for each formula, run the
     plain sampler from uniform starts and label every variable with the
     fraction of chains whose best assignment sets it.  Returns device tensors
-    x [rows][32] (bf16 bits) and y [rows]."""
+    x [rows][32] (bf16 bits) and y [rows].  With a FormulaPool the next
+    batch of formulas is generated while the GPU labels the current one."""
     import torch
     W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
     temps = wl.default_temperatures(chains, 2)
     xs, ys = [], []
-    for lo in range(0, n_formulas, batch):
+    src = pool if pool is not None else FormulaPool(0)
+    t_start = time.time()
+    starts = list(range(0, n_formulas, batch))
+    pending = src.submit(min(batch, n_formulas), n_vars, seed, first) if starts else None
+    for j, lo in enumerate(starts):
         k = min(batch, n_formulas - lo)
-        tables = _formulas(k, n_vars, seed, first + lo)
+        tables = pending()
+        if j + 1 < len(starts):
+            nlo = starts[j + 1]
+            pending = src.submit(min(batch, n_formulas - nlo), n_vars, seed, first + nlo)
         plan = hp.Plan(tables, [n_vars] * k, W, b, chains=chains, temps=temps, precision="f32",
                        seed=seed + 1000 * (first + lo))
         st = plan.new_state([wl.initial_state(chains, n_vars, seed, tag=first + lo + f) for f in range(k)])
@@ -178,7 +214,7 @@ def make_dataset(n_formulas, n_vars=2048, seed=4, chains=32, sweeps=500, batch=2
         torch.cuda.synchronize()
         plan.free()
         if log:
-            log(f"labelled {lo + k}/{n_formulas} formulas")
+            log(f"labelled {lo + k}/{n_formulas} formulas ({time.time() - t_start:.1f} s)")
     return torch.cat(xs), torch.cat(ys)
 
 
@@ -248,13 +284,16 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=256)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--out", default=WEIGHTS_JSON)
+    ap.add_argument("--workers", type=int, default=16, help="host processes generating formulas")
     args = ap.parse_args(argv)
+    pool = FormulaPool(args.workers)      # forked before the GPU is used
 
     def log(msg):
         print(f"[learned] {msg}", file=sys.stderr, flush=True)
 
     t0 = time.time()
-    x, y = make_dataset(args.instances, args.n_vars, args.seed, sweeps=args.label_sweeps, log=log)
+    x, y = make_dataset(args.instances, args.n_vars, args.seed, sweeps=args.label_sweeps, log=log, pool=pool)
+    pool.close()
     t1 = time.time()
     net = MLP(seed=args.seed)
     losses = train(net, x, y, epochs=args.epochs, log=log)

@@ -14,6 +14,7 @@ Tolerance classes (per result):
               contributions of size <= ~10 gives |dx| <= 1e-4 * 2^-24 * 100,
               far below; the bound is dominated by the FP32 sigmoid).
 """
+import os
 import sys
 
 import numpy as np
@@ -66,3 +67,22 @@ def teacher_forced_sweep(plan, state, f, ost, op, temps, *, alpha, seed, prec, c
     assert rel.max() <= NU_RTOL[prec], f"nu rel err {rel.max():.3e}"
     # continue the trajectory from the oracle's state (teacher forcing)
     return ties
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_lines(name):
+    """Non-comment lines of a fixture under tests/golden/."""
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return [ln.strip() for ln in fh if ln.strip() and not ln.lstrip().startswith("#")]
+
+
+def golden_fields(name):
+    """``key: values`` lines of a fixture as a dict of strings."""
+    out = {}
+    for ln in golden_lines(name):
+        if ":" in ln and "->" not in ln:
+            k, v = ln.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out

@@ -17,6 +17,7 @@ import pytest
 from oracle import philox as PH
 from oracle import rbmsat as R
 from paper_2311_02101_amd import workload as wl
+from tests.parity import golden_fields, golden_lines
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -77,13 +78,18 @@ def rocrand_probe():
 # ---------------------------------------------------------------------------
 
 # Known-answer vectors published with the Random123 reference implementation
-# of Salmon et al. (SC'11) for Philox4x32 with 10 rounds: (counter, key, out).
-KAT = [
-    ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
-    ((0xffffffff,) * 4, (0xffffffff, 0xffffffff), (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
-    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
-     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
-]
+# of Salmon et al. (SC'11) for Philox4x32 with 10 rounds (fixture with its
+# citation): (counter, key, out).
+def _kat():
+    out = []
+    for ln in golden_lines("philox4x32_10_kat.txt"):
+        left, right = ln.split(":")
+        w = [int(x, 16) for x in left.split()]
+        out.append((tuple(w[:4]), tuple(w[4:6]), tuple(int(x, 16) for x in right.split())))
+    return out
+
+
+KAT = _kat()
 
 
 @pytest.mark.parametrize("ctr,key,out", KAT)
@@ -228,22 +234,40 @@ def test_negated_literals_count_as_satisfied():
 
 def test_worked_example_clause_column():
     # Sec. 3.3: the column (1, 2, -3, 4) is v1 or v2 or not v3 or v4
-    T = np.array([[1], [2], [-3], [4]])
+    g = golden_fields("sec3_3_clause_column.txt")
+    T = np.array([[int(x)] for x in g["column"].split()])
     p = R.plan(T, 4, np.zeros((4, 5)), np.zeros(5))
-    assert list(p.pol[:, 0]) == [1, 1, -1, 1] and list(p.idx[:, 0]) == [0, 1, 2, 3]
+    assert list(p.pol[:, 0]) == [int(x) for x in g["polarity"].split()]
+    assert list(p.idx[:, 0]) == [int(x) for x in g["index0"].split()]
     V = bits(None, 4).astype(np.uint8)
-    only_false = [tuple(v) for v in V if R.clause_count(v[None], p)[0] == 0]
-    assert only_false == [(0, 0, 1, 0)]
+    only_false = [tuple(int(x) for x in v) for v in V if R.clause_count(v[None], p)[0] == 0]
+    assert only_false == [tuple(int(x) for x in g["falsified_by"].split())]
 
 
 def test_worked_example_unit_propagation_formula():
     # Sec. 3.4: (a or b or c) and (not c or not d); a = b = False forces c,
-    # which forces d = False.  Counts at (a,b,c,d) = (0,0,1,0) and (0,0,1,1).
-    T = wl.pad_clauses([[1, 2, 3], [-3, -4]], 3)
+    # which forces d = False.
+    name = "sec3_4_unit_propagation.txt"
+    clauses = [[int(x) for x in part.split()] for part in golden_fields(name)["clauses"].split("|")]
+    T = wl.pad_clauses(clauses, 3)
     p = R.plan(T, 4, np.zeros((3, 3)), np.zeros(3))
-    assert R.clause_count(np.array([[0, 0, 1, 0]], np.uint8), p)[0] == 2
-    assert R.clause_count(np.array([[0, 0, 1, 1]], np.uint8), p)[0] == 1
-    assert R.clause_count(np.array([[0, 0, 0, 0]], np.uint8), p)[0] == 1
+    cases = [ln.split("->") for ln in golden_lines(name) if "->" in ln]
+    assert len(cases) == 3
+    for a, want in cases:
+        v = np.array([[int(x) for x in a.split()]], np.uint8)
+        assert R.clause_count(v, p)[0] == int(want)
+
+
+def test_pretraining_targets_match_the_appendix():
+    g = golden_fields("appendix_pretraining_targets.txt")
+    assert tuple(float(x) for x in g["pair"].split()) == wl.FSTAR_PAIR
+    assert tuple(float(x) for x in g["sixteen"].split()) == wl.FSTAR_16
+    # every listed target has a fitted canonical OR-gate RBM for K = 3..7
+    listed = set(float(x) for k in ("pair", "eight", "sixteen") for x in g[k].split())
+    for K in range(3, 8):
+        for f in sorted(listed):
+            W, b, res = wl.pretrained_rbm(K, (f,))
+            assert W.shape == (1, K, wl.hidden_units_for(K)) and res[0] < 0.05 * f
 
 
 def test_padding_by_repetition_keeps_satisfying_set():
