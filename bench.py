@@ -39,6 +39,7 @@ if ROOT not in sys.path:
 PHILOX_SLOTS = 40
 DRAW_SLOTS = 2
 PEAK_SLOTS = 256 * 64 * 2.4e9
+MFMA_BF16_PEAK = 2.5e15          # dense BF16 MFMA, MI355X
 
 
 def chain_sweep_work(n_vars, n_clauses, L):
@@ -52,7 +53,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "mixed"])
     ap.add_argument("--workload", default="plain_n4096_b64")
     ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--threads", type=int, default=0)
@@ -165,6 +166,13 @@ def main(argv=None):
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "philox_calls_per_chain_sweep": calls, "draws_per_chain_sweep": draws},
     }
+    if args.precision == "mixed":
+        # two v_mfma_f32_32x32x16_bf16 per 32 clauses per chain-sweep (hidden
+        # logits and contributions, four BF16 limb pairs each)
+        tiles = sum(-(-t.shape[1] // 32) for t in w.tables)
+        mfma_flops = tiles * 2 * (32 * 32 * 16 * 2) * B * args.sweeps
+        out["mfma"] = {"flops_per_launch": mfma_flops, "achieved_tflops": mfma_flops / avg_launch_s / 1e12,
+                       "peak_tflops": MFMA_BF16_PEAK / 1e12, "frac": mfma_flops / avg_launch_s / MFMA_BF16_PEAK}
     if args.cpu_sweeps > 0:
         out["cpu_baseline"] = cpu_baseline(w, plan, args.cpu_sweeps, args.precision, dev)
     print(json.dumps(out), flush=True)

@@ -42,10 +42,23 @@ typedef enum {
     HP_EUNSUPPORTED = -4   /* valid input outside what this build handles         */
 } hp_status;
 
+/* Arithmetic of the sweep.  HP_FP64 and HP_FP32 take the hidden draws from
+ * per-temperature threshold tables and the contributions from fixed-point
+ * tables (both prepared in FP64); the visible sigmoid and variance EMA run in
+ * the named precision.  HP_MIXED_BF16 is the form of the appendix
+ * ("Precision"), where the accelerator multiplies in bfloat16: per clause, the
+ * hidden logits z = b + W^T lit and the contributions l = W h are computed
+ * every sweep as v_mfma_f32_32x32x16_bf16 products with W split into eight
+ * BF16 limbs (each limb pair exact in FP32, four pairs = 64 bits), hidden
+ * draws decided from an FP32 sigmoid unless U is within 16 * 2^-24 of it
+ * (then the FP64 threshold decides), contributions recombined in FP64 onto
+ * the fixed-point grid; visible update and EMA in FP64, nu is double.  Its
+ * samples equal HP_FP64's.  It runs the push launch only (no pull kernel, no
+ * split) and returns HP_EUNSUPPORTED otherwise. */
 typedef enum {
-    HP_FP64 = 0,           /* logits, sigmoid and variance EMA in FP64            */
-    HP_FP32 = 1,           /* the same in FP32 (tables prepared in FP64)          */
-    HP_MIXED_BF16 = 2      /* reserved: BF16-limb MFMA contraction                */
+    HP_FP64 = 0,
+    HP_FP32 = 1,
+    HP_MIXED_BF16 = 2
 } hp_precision;
 
 /* The formula batch: signed 1-based literal table (Sec. 3.3).  Column c of
@@ -122,7 +135,7 @@ typedef struct {
     int64_t total_vars;             /* sum N_f the buffers were sized for (checked)     */
     int32_t n_formulas;             /* F the buffers were sized for (checked)           */
     int32_t chains;                 /* B the buffers were sized for (checked)           */
-    int32_t nu_bytes;               /* sizeof(*nu): 8 or 4 (checked against precision)  */
+    int32_t nu_bytes;               /* sizeof(*nu): 4 for HP_FP32, else 8 (checked)     */
 } hp_state;
 
 typedef struct hp_plan_s *hp_plan_t;

@@ -76,10 +76,101 @@ void release(Plan *p) {
     (void)hipFree(p->tab.thr);
     (void)hipFree(p->tab.g64);
     (void)hipFree(p->tab.g32);
+    (void)hipFree(p->tab.mfma);
     delete p;
 }
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Variable groups (of 4) per thread whose variance EMA stays in registers:
+// 1 or 2, else 0 (EMA in global memory).  The mixed-precision kernel keeps
+// at most one group in registers (two spill next to its MFMA operands).
+int vpt_for(int groups, int threads, bool mixed) {
+    if (groups <= threads) return 1;
+    if (groups <= 2 * threads && !mixed) return 2;
+    return 0;
+}
+
+// Split a column of 8 weights into kLimbs BF16 limbs on the column's common
+// exponent grid (see the mixed-precision operand layout): limb j of entry i
+// is q * 2^(E - 8(j+1)) with |q| <= 256, rounded to nearest from what the
+// earlier limbs left.  Returns false if a limb is not exactly a BF16 value.
+bool split_limbs(const double col[8], double limb[kLimbs][8]) {
+    double mx = 0.0;
+    for (int i = 0; i < 8; ++i) mx = std::max(mx, std::fabs(col[i]));
+    for (int j = 0; j < kLimbs; ++j)
+        for (int i = 0; i < 8; ++i) limb[j][i] = 0.0;
+    if (mx == 0.0) return true;
+    int E = 0;
+    (void)std::frexp(mx, &E);          // mx < 2^E
+    double r[8];
+    for (int i = 0; i < 8; ++i) r[i] = col[i];
+    for (int j = 0; j < kLimbs; ++j) {
+        const double grid = std::ldexp(1.0, E - 8 * (j + 1));
+        for (int i = 0; i < 8; ++i) {
+            const double q = std::nearbyint(r[i] / grid);
+            if (std::fabs(q) > 256.0) return false;
+            limb[j][i] = q * grid;
+            r[i] -= limb[j][i];
+            const float f = (float)limb[j][i];
+            uint32_t bits;
+            std::memcpy(&bits, &f, 4);
+            if ((double)f != limb[j][i] || (bits & 0xffffu) != 0u) return false;
+        }
+    }
+    return true;
+}
+
+uint16_t bf16_bits_exact(double x) {
+    const float f = (float)x;
+    uint32_t bits;
+    std::memcpy(&bits, &f, 4);
+    return (uint16_t)(bits >> 16);
+}
+
+// Per-lane A operands of the two mixed-precision products for every
+// temperature: [T][2][64] uint4 (8 BF16 values each).  Lane l supplies row
+// l % 32 = 8g + (unit or slot) and K entries 8h .. 8h+7 with h = l / 32, i.e.
+// limb 2g + h of the 8 weights of that row.
+bool mfma_operands(const double *W, const double *b, int T, int K, int L, std::vector<uint4> &out) {
+    out.assign((size_t)T * 2 * 64, make_uint4(0, 0, 0, 0));
+    for (int tau = 0; tau < T; ++tau) {
+        const double *Wt = W + (size_t)tau * K * L;
+        // product 1: column u = (W[0..K-1][u], 0.., b[u] at position 7)
+        for (int u = 0; u < kMaxL; ++u) {
+            double col[8] = {0, 0, 0, 0, 0, 0, 0, 0}, limb[kLimbs][8];
+            if (u < L) {
+                for (int k = 0; k < K; ++k) col[k] = Wt[k * L + u];
+                col[7] = b[(size_t)tau * L + u];
+            }
+            if (!split_limbs(col, limb)) return false;
+            for (int g = 0; g < kLimbs / 2; ++g)
+                for (int h = 0; h < 2; ++h) {
+                    uint16_t e[8];
+                    for (int k = 0; k < 8; ++k) e[k] = bf16_bits_exact(limb[2 * g + h][k]);
+                    out[((size_t)tau * 2 + 0) * 64 + h * 32 + g * 8 + u] =
+                        make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
+                                   e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
+                }
+        }
+        // product 2: column k = (W[k][0..L-1])
+        for (int k = 0; k < kMaxL; ++k) {
+            double col[8] = {0, 0, 0, 0, 0, 0, 0, 0}, limb[kLimbs][8];
+            if (k < K)
+                for (int u = 0; u < L; ++u) col[u] = Wt[k * L + u];
+            if (!split_limbs(col, limb)) return false;
+            for (int g = 0; g < kLimbs / 2; ++g)
+                for (int h = 0; h < 2; ++h) {
+                    uint16_t e[8];
+                    for (int u = 0; u < 8; ++u) e[u] = bf16_bits_exact(limb[2 * g + h][u]);
+                    out[((size_t)tau * 2 + 1) * 64 + h * 32 + g * 8 + k] =
+                        make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
+                                   e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
+                }
+        }
+    }
+    return true;
+}
 
 }  // namespace
 }  // namespace hp
@@ -120,10 +211,10 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     const int B = opts->chains;
     if (B < 1) return fail(HP_EINVAL, "chains must be >= 1");
     if (!(opts->alpha >= 0.0 && opts->alpha <= 1.0)) return fail(HP_EINVAL, "alpha must be in [0,1]");
-    if (opts->precision == HP_MIXED_BF16)
-        return fail(HP_EUNSUPPORTED, "mixed BF16 precision is not available in this build");
-    if (opts->precision != HP_FP64 && opts->precision != HP_FP32)
+    if (opts->precision != HP_FP64 && opts->precision != HP_FP32 && opts->precision != HP_MIXED_BF16)
         return fail(HP_EINVAL, "unknown precision");
+    if (opts->precision == HP_MIXED_BF16 && (opts->kernel == HP_KERNEL_PULL || opts->split >= 2))
+        return fail(HP_EUNSUPPORTED, "mixed BF16 precision runs the push launch without split only");
     if (opts->threads != 0 && (opts->threads < kWave || opts->threads > 1024 || opts->threads % kWave))
         return fail(HP_EINVAL, "threads must be 0 or a multiple of 64 in [64, 1024]");
     if (opts->kernel < HP_KERNEL_AUTO || opts->kernel > HP_KERNEL_PUSH)
@@ -280,7 +371,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     int max_lds = 0;
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
-    const size_t real_bytes = opts->precision == HP_FP64 ? 8 : 4;
+    const size_t real_bytes = opts->precision == HP_FP32 ? 4 : 8;
+    const bool mixed = opts->precision == HP_MIXED_BF16;
     p->threads = opts->threads;
 
     // --- kernel variant and size class per formula, work list, buckets ---
@@ -291,6 +383,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     auto kind_of = [&](int f) -> int {
         int32_t vo, xo, ho;
         const bool fx_ok = fx_shift >= 40;
+        if (mixed)   // contributions come from MFMA: only the threshold table in LDS
+            return fx_ok && lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds ? kBucketWide : -1;
         if (opts->kernel != HP_KERNEL_PULL && fx_ok) {
             if (lds_bytes_push(fd[f].n, false, &vo, &xo) <= (size_t)max_lds) return kBucketPush;
             if (lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds) return kBucketWide;
@@ -360,7 +454,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         }
         bk.threads = t;
         const int groups = (bk.max_n + 3) / 4;
-        bk.vpt = groups <= t ? 1 : (groups <= 2 * t ? 2 : 0);
+        bk.vpt = vpt_for(groups, t, mixed);
         // persistent grid when the items outnumber the resident workgroups
         const int occ = bucket_occupancy(*p, bk);
         const int64_t capacity = (int64_t)p->cus * std::max(occ, 1);
@@ -436,6 +530,15 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
     HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kMaxL * sizeof(int64_t)), "alloc gfx");
     HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kMaxL * kHidMasks * sizeof(int64_t)), "alloc gpad");
+    if (mixed) {
+        std::vector<uint4> ops;
+        if (!mfma_operands(rbm->W, rbm->b, T, K, L, ops)) {
+            (void)hipStreamSynchronize(s);
+            release(p);
+            return fail(HP_EUNSUPPORTED, "a weight does not split into BF16 limbs (exponent out of range)");
+        }
+        HP_TRY(upload(&p->tab.mfma, ops, s), "upload MFMA operands");
+    }
     HP_TRY(hipMalloc((void **)&p->d_err, sizeof(int32_t)), "alloc error flag");
     HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_err), 1, s), "clear error flag");
     HP_TRY(hipMalloc((void **)&p->d_tabflag, sizeof(int32_t)), "alloc table flag");
@@ -478,7 +581,7 @@ hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *str
     if (!st->v || !st->nu || !st->s_max || !st->best || !st->t) return fail(HP_EINVAL, "null state buffer");
     if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B)
         return fail(HP_EINVAL, "state shape does not match the plan");
-    const int want = p->precision == HP_FP64 ? 8 : 4;
+    const int want = p->precision == HP_FP32 ? 4 : 8;
     if (st->nu_bytes != want) return fail(HP_EINVAL, "nu element size does not match the precision");
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -525,7 +628,7 @@ hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *st
     if (!p || !st) return fail(HP_EINVAL, "null argument");
     if (n_sweeps < 1) return fail(HP_EINVAL, "n_sweeps must be >= 1");
     if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B ||
-        st->nu_bytes != (p->precision == HP_FP64 ? 8 : 4))
+        st->nu_bytes != (p->precision == HP_FP32 ? 4 : 8))
         return fail(HP_EINVAL, "state shape does not match the plan");
     if (p->split > 1) return HP_OK;    // the split launch keeps its full-size workgroups
     hipStream_t s = (hipStream_t)stream;
@@ -541,7 +644,7 @@ hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *st
             bk = orig;
             bk.threads = t;
             const int groups = (bk.max_n + 3) / 4;
-            bk.vpt = groups <= t ? 1 : (groups <= 2 * t ? 2 : 0);
+            bk.vpt = vpt_for(groups, t, p->precision == HP_MIXED_BF16);
             const int occ = bucket_occupancy(*p, bk);
             if (occ < 1) continue;     // this shape cannot launch
             const int64_t capacity = (int64_t)p->cus * occ;

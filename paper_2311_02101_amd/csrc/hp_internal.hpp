@@ -49,7 +49,22 @@ struct DeviceTables {
     float *g32 = nullptr;      // [T][256][8]
     int64_t *gfx = nullptr;    // [T][256][8]
     int64_t *gpad = nullptr;   // [T][8][256]
+    uint4 *mfma = nullptr;     // [T][2][64] per-lane BF16 limb operands (mixed precision)
 };
+
+// Mixed-precision contraction operands.  Both per-clause products are MFMA
+// v_mfma_f32_32x32x16_bf16 with the clauses as the 32 columns and the
+// constant weights as the 32 x 16 A operand:
+//   hidden logits   z[u]  = b[u] + sum_k lit[k] W[k][u]  (bias as input 7 = 1)
+//                   A rows (g, u) = 8g + u, K index = (h, k) = 8h + k
+//   contributions   l[k]  = sum_u h[u] W[k][u]
+//                   A rows (g, k) = 8g + k, K index = (h, u) = 8h + u
+// Entry (g, h) holds BF16 limb j = 2g + h of the weight.  Limbs of one
+// column share the exponent grid of the column's largest magnitude 2^E:
+// limb j is a multiple of 2^(E - 8(j+1)) of magnitude <= 2^(E - 8j), so a
+// product over 8 binary inputs of one limb pair (g) is exact in FP32 and the
+// four pairs carry 64 bits of every weight.
+constexpr int kLimbs = 8;
 
 // Clause record of the push kernel: 8 x 16-bit slots in a uint4.  Slots
 // 0..6 hold literal k as (0-based variable index) | (negated << 15); slot 7
@@ -74,6 +89,7 @@ struct SweepParams {
     const Real *G;               // [T][256][8]
     const int64_t *gfx;          // [T][256][8]
     const int64_t *gpad;         // [T][8][256]
+    const uint4 *mfma;           // [T][2][64] mixed-precision A operands
     const int32_t *temp_of_chain;
     uint8_t *v;
     Real *nu;

@@ -419,6 +419,128 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
     return cnt;
 }
 
+// ---- mixed precision: the per-clause products on MFMA ---------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+// 8 binary inputs (bit i of `bits`) as BF16 0.0 / 1.0, element i = input i
+__device__ __forceinline__ bf16x8_t bits_bf16x8(uint32_t bits) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t lo = (uint32_t)((int32_t)(bits << (31 - 2 * j)) >> 31);       // 0 or ~0
+        const uint32_t hi = (uint32_t)((int32_t)(bits << (30 - 2 * j)) >> 31);
+        w[j] = (lo & 0x00003F80u) | (hi & 0x3F800000u);
+    }
+    return __builtin_bit_cast(bf16x8_t, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
+__device__ __forceinline__ int64_t shfl_xor_i64(int64_t v, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)v, m, 64), hi = __shfl_xor((int)(v >> 32), m, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Hidden-draw margin: |p32 - p| <= 3e-7 for the FP32 logit (sum of four
+// exact limb-pair products) and the FP32 sigmoid (v_exp_f32, v_rcp_f32);
+// a draw whose U lies within 16 * 2^-24 (9.5e-7) of p32 is taken from the
+// FP64 threshold table instead, so every hidden bit equals the FP64 rule.
+constexpr float kDrawMargin24 = 16.0f;
+
+// Clause phase with the two per-clause contractions on MFMA.  A wave takes
+// 32 clauses at a time; lane l works on clause tb + l % 32, lanes l and l+32
+// on the same clause: the low half draws hidden units 0..3 (Philox block
+// 2c) and scatters slots 0..3, the high half units 4..7 (block 2c+1) and
+// slots 4..6.  The MFMA result lands in that layout (register i = limb pair
+// i / 4 of unit or slot 4h + i % 4), so the limb pairs are summed in
+// registers.  Counts, hidden bits and fixed-point contributions equal the
+// table path's.
+template <bool kSample>
+__device__ __forceinline__ int clause_phase_mfma(const PushLds &L, const uint4 *__restrict__ rec,
+                                                 const uint32_t *__restrict__ orig, int C, int tid, int NT,
+                                                 uint32_t tlo, uint32_t thi, uint32_t chain, Key2 key,
+                                                 uint32_t nbh, uint32_t full, uint32_t lmask, int K,
+                                                 bf16x8_t a1, bf16x8_t a2, double inv_scale) {
+    const int lane = tid & (kWave - 1), wave = tid / kWave, n_waves = NT / kWave;
+    const int half = lane >> 5;
+    int cnt = 0;
+    for (int tb = wave * 32; tb < C; tb += n_waves * 32) {      // uniform over the wave
+        const int c = tb + (lane & 31);
+        const bool act = c < C;
+        uint4 r = make_uint4(0, 0, 0, 0);
+        uint32_t oc = 0;
+        if (act) {
+            r = rec[c];
+            oc = orig[c];
+        }
+        const uint32_t len = (r.w >> 16) & 7u;
+        const uint32_t negm = r.w >> 19;
+        const uint32_t e[7] = {r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16,
+                               r.z & 0xffffu, r.z >> 16, r.w & 0xffffu};
+        uint32_t m = 0;
+        if (act) {
+            m = L.v[e[0] & 0x7fffu];
+            if (len > 1) m |= (uint32_t)L.v[e[1] & 0x7fffu] << 1;
+            if (len > 2) m |= (uint32_t)L.v[e[2] & 0x7fffu] << 2;
+            if (len > 3) m |= (uint32_t)L.v[e[3] & 0x7fffu] << 3;
+            if (len > 4) m |= (uint32_t)L.v[e[4] & 0x7fffu] << 4;
+            if (len > 5) m |= (uint32_t)L.v[e[5] & 0x7fffu] << 5;
+            if (len > 6) m |= (uint32_t)L.v[e[6] & 0x7fffu] << 6;
+            m ^= negm;
+            m |= (m & 1u) ? (full & ~((1u << len) - 1u)) : 0u;
+            if (half == 0) cnt += (m != 0u);
+        }
+        if (!kSample) continue;
+        // ---- hidden logits z = b + W^T lit, limb pairs summed in FP32 ----
+        const f32x16_t d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bits_bf16x8(act ? (m | 0x80u) : 0u),
+                                                                    f32x16_t{}, 0, 0, 0);
+        const uint4 rw = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | (oc * nbh + (uint32_t)half), thi), key);
+        const uint32_t w4[4] = {rw.x, rw.y, rw.z, rw.w};
+        uint32_t nh = 0, amb = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float z = ((d1[q] + d1[4 + q]) + d1[8 + q]) + d1[12 + q];
+            const float p = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+            const float d = fmaf(p, -16777216.0f, (float)(w4[q] >> 8));   // (U - p) 2^24
+            nh |= (d < 0.0f ? 1u : 0u) << q;
+            amb |= (fabsf(d) <= kDrawMargin24 ? 1u : 0u) << q;
+        }
+        if (amb != 0u && act) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((amb >> q) & 1u) {
+                    const uint32_t bit = w4[q] <= L.thr[m * kMaxL + 4 * half + q] ? 1u : 0u;
+                    nh = (nh & ~(1u << q)) | (bit << q);
+                }
+        }
+        const uint32_t other = (uint32_t)__shfl_xor((int)nh, 32, 64);
+        const uint32_t n = act ? ((half ? (other | (nh << 4)) : (nh | (other << 4))) & lmask) : 0u;
+        // ---- contributions l = W h, limb pairs summed in FP64, fixed point ----
+        const f32x16_t d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, bits_bf16x8(n), f32x16_t{}, 0, 0, 0);
+        int64_t fx[4], pad = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * half + q;
+            const double lk = (((double)d2[q] + (double)d2[4 + q]) + (double)d2[8 + q]) + (double)d2[12 + q];
+            fx[q] = k < K ? (int64_t)llrint(lk * inv_scale) : 0;
+            if (k >= (int)len && k < K) pad += fx[q];    // padding copies of literal 0
+        }
+        pad += shfl_xor_i64(pad, 32);
+        if (act) {
+            if (half == 0) {
+                push_add(L.x, e[0], fx[0] + pad);
+#pragma unroll
+                for (int q = 1; q < 4; ++q)
+                    if (q < (int)len) push_add(L.x, e[q], fx[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (4 + q < (int)len) push_add(L.x, e[4 + q], fx[q]);
+            }
+        }
+    }
+    return cnt;
+}
+
 // Visible update of one variable from its fixed-point logit: sigmoid, EMA,
 // Bernoulli draw U < rho with U = (word >> 8) 2^-24.
 template <typename Real>
@@ -444,7 +566,7 @@ __device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, i
 // item w.  Otherwise the grid is persistent: workgroups take items from an
 // atomic counter (zeroed before the launch) until all `count` items are done,
 // largest formulas first, so uneven sizes balance over the resident grid.
-template <typename Real, int VPT, bool kWide>
+template <typename Real, int VPT, bool kWide, bool kMfma = false>
 __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, uint32_t *queue, int count) {
     extern __shared__ __align__(16) unsigned char lds[];
     int *s_item = reinterpret_cast<int *>(lds + (kWide ? kWideCntOff : kPushCntOff)) + 63;
@@ -487,6 +609,11 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
             L.v[i] = P.v[sbase + i];
             L.x[i] = negcnt[i];
         }
+        bf16x8_t a1 = {}, a2 = {};
+        if (kMfma) {
+            a1 = __builtin_bit_cast(bf16x8_t, P.mfma[((size_t)tau * 2 + 0) * kWave + (tid & (kWave - 1))]);
+            a2 = __builtin_bit_cast(bf16x8_t, P.mfma[((size_t)tau * 2 + 1) * kWave + (tid & (kWave - 1))]);
+        }
         constexpr int VR = VPT > 0 ? VPT : 1;
         Real nu[VR][4];
         int32_t ncr[VR][4];
@@ -506,8 +633,15 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         for (int64_t s = 0; s < S; ++s) {
             const uint64_t t = (uint64_t)(t0 + s);
             const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-            const int cnt = sample ? clause_phase<true>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
-                                   : clause_phase<false>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
+            int cnt;
+            if (kMfma)
+                cnt = sample ? clause_phase_mfma<true>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full,
+                                                       lmask, P.K, a1, a2, 1.0 / fx_scale)
+                             : clause_phase_mfma<false>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh,
+                                                        full, lmask, P.K, a1, a2, 1.0 / fx_scale);
+            else
+                cnt = sample ? clause_phase<true>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
+                             : clause_phase<false>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
             const int total = block_total(L, cnt, tid, NT);
             const bool improved = total > smax;
             if (improved) smax = total;
@@ -876,6 +1010,14 @@ const void *push_kernel_ptr(int vpt, bool wide) {
     }
 }
 
+const void *mixed_kernel_ptr(int vpt) {
+    switch (vpt) {
+        case 1: return (const void *)sweep_push_kernel<double, 1, true, true>;
+        case 2: return (const void *)sweep_push_kernel<double, 2, true, true>;
+        default: return (const void *)sweep_push_kernel<double, 0, true, true>;
+    }
+}
+
 template <typename Real>
 const void *pull_kernel_ptr(int vpt) {
     switch (vpt) {
@@ -900,13 +1042,18 @@ hipError_t set_limits_t(int bytes) {
 
 hipError_t set_kernel_lds_limits(int bytes) {
     hipError_t e = set_limits_t<double>(bytes);
-    return e != hipSuccess ? e : set_limits_t<float>(bytes);
+    if (e == hipSuccess) e = set_limits_t<float>(bytes);
+    for (int vpt = 0; vpt < 3 && e == hipSuccess; ++vpt)
+        e = hipFuncSetAttribute(mixed_kernel_ptr(vpt), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
 }
 
 int bucket_occupancy(const Plan &p, const Bucket &b) {
     const void *k;
     if (b.kind == kBucketPull)
-        k = p.precision == HP_FP64 ? pull_kernel_ptr<double>(b.vpt) : pull_kernel_ptr<float>(b.vpt);
+        k = p.precision == HP_FP32 ? pull_kernel_ptr<float>(b.vpt) : pull_kernel_ptr<double>(b.vpt);
+    else if (p.precision == HP_MIXED_BF16)
+        k = mixed_kernel_ptr(b.vpt);
     else
         k = p.precision == HP_FP64 ? push_kernel_ptr<double>(b.vpt, b.kind == kBucketWide)
                                    : push_kernel_ptr<float>(b.vpt, b.kind == kBucketWide);
@@ -947,6 +1094,7 @@ SweepParams<Real> sweep_params(const Plan &p, const hp_state &st, int64_t n_swee
     P.negcnt = p.d_negcnt;
     P.gfx = p.tab.gfx;
     P.gpad = p.tab.gpad;
+    P.mfma = p.tab.mfma;
     P.fx_scale = std::ldexp(1.0, -p.fx_shift);
     P.thr = p.tab.thr;
     P.G = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(p.tab.g64)
@@ -992,14 +1140,15 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
         if (e != hipSuccess) return e;
         grid = b.grid;
     }
-    hipLaunchKernelGGL((void (*)(SweepParams<Real>, uint32_t *, int))push_kernel_ptr<Real>(b.vpt, wide), dim3(grid),
-                       dim3(b.threads), b.lds, s, P, queue, b.count);
+    const void *kern = p.precision == HP_MIXED_BF16 ? mixed_kernel_ptr(b.vpt) : push_kernel_ptr<Real>(b.vpt, wide);
+    hipLaunchKernelGGL((void (*)(SweepParams<Real>, uint32_t *, int))kern, dim3(grid), dim3(b.threads), b.lds, s, P,
+                       queue, b.count);
     return hipGetLastError();
 }
 
 hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
-    return p.precision == HP_FP64 ? launch_bucket_t<double>(p, b, st, n_sweeps, s)
-                                  : launch_bucket_t<float>(p, b, st, n_sweeps, s);
+    return p.precision == HP_FP32 ? launch_bucket_t<float>(p, b, st, n_sweeps, s)
+                                  : launch_bucket_t<double>(p, b, st, n_sweeps, s);
 }
 
 template <typename Real>

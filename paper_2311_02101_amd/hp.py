@@ -230,7 +230,7 @@ class State:
         flat = np.concatenate([np.asarray(v, dtype=np.uint8).reshape(-1) for v in v0_list])
         if flat.size != plan.total_vars * plan.B:
             raise ValueError("initial states do not match the plan's sizes")
-        ndt = torch.float64 if plan.precision == "f64" else torch.float32
+        ndt = torch.float32 if plan.precision == "f32" else torch.float64
         v = torch.from_numpy(flat.copy()).to(device)
         nu = torch.full((flat.size,), 0.25, dtype=ndt, device=device)
         s_max = torch.zeros(plan.F * plan.B, dtype=torch.int32, device=device)

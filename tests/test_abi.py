@@ -76,7 +76,9 @@ CASES = [
     ("negative temperature", dict(temps=[-1, 0]), hp.HP_EINVAL),
     ("bad thread count", dict(threads=100), hp.HP_EINVAL),
     ("unknown precision", dict(prec=7), hp.HP_EINVAL),
-    ("mixed precision unavailable", dict(prec=hp.HP_MIXED_BF16), hp.HP_EUNSUPPORTED),
+    ("mixed precision with the pull kernel", dict(prec=hp.HP_MIXED_BF16, kernel=hp.KERNEL["pull"]),
+     hp.HP_EUNSUPPORTED),
+    ("mixed precision with a split", dict(prec=hp.HP_MIXED_BF16, split=2), hp.HP_EUNSUPPORTED),
     ("split not a power of two", dict(split=3), hp.HP_EINVAL),
     ("split too large", dict(split=32), hp.HP_EINVAL),
     ("unknown kernel variant", dict(kernel=5), hp.HP_EINVAL),
