@@ -735,7 +735,9 @@ __device__ __forceinline__ int32_t xload(const int32_t *p) {
 // workgroup's arrival is counted; the exchange loads that follow the barrier
 // are issued only after the completed count has been observed.  The wait is
 // bounded: on timeout the error flag is raised and the workgroup continues
-// (its results are then void), so no launch can hang.
+// (its results are then void); once the flag is up no barrier of the launch
+// waits any more, so a launch whose barriers cannot complete ends after one
+// time-out instead of one per barrier.
 __device__ __forceinline__ void group_barrier(uint32_t *ctr, uint32_t target, int32_t *err) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -748,6 +750,8 @@ __device__ __forceinline__ void group_barrier(uint32_t *ctr, uint32_t target, in
                 __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
+            if ((spins & 1023u) == 0u && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
         }
     }
     __syncthreads();

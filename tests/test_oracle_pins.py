@@ -251,7 +251,7 @@ def test_worked_example_unit_propagation_formula():
     clauses = [[int(x) for x in part.split()] for part in golden_fields(name)["clauses"].split("|")]
     T = wl.pad_clauses(clauses, 3)
     p = R.plan(T, 4, np.zeros((3, 3)), np.zeros(3))
-    cases = [ln.split("->") for ln in golden_lines(name) if "->" in ln]
+    cases = [ln.split("->") for ln in golden_lines(name) if "->" in ln and not ln.startswith("up:")]
     assert len(cases) == 3
     for a, want in cases:
         v = np.array([[int(x) for x in a.split()]], np.uint8)
