@@ -255,6 +255,37 @@ hp_status hp_init_chains(hp_plan_t plan, const float *q, int32_t chain_lo, int32
  * example state->best): device [sum N_f] floats in variable order. */
 hp_status hp_chain_mean(hp_plan_t plan, const uint8_t *a, float *out, void *stream);
 
+/* ---- Prioritized unit propagation and the exchange (Sec. 3.4) ------------
+ * Sec. 3.4 improves sampled assignments on the CPU: the floor(N/2) variables
+ * with the highest variance average nu keep their sampled values and the
+ * others are recomputed by unit propagation; the appendix program sends
+ * (v, nu) to the host periodically and, some sweeps later, stacks the
+ * returned assignments under the current ones and keeps the best B. */
+
+/* Host.  New assignments of n_chains chains of formula `formula`:
+ * v, out: HOST [n_chains][N_f] bytes (0/1); nu: HOST [n_chains][N_f] doubles.
+ * Per chain: variables ordered by nu descending (ties by index); the first
+ * floor(N/2) keep their values; every clause is examined once in clause
+ * order (a clause with no true literal and one unassigned literal makes it
+ * true; with none unassigned it is a conflict and stays unsatisfied); then
+ * FIFO propagation (a dequeued variable re-examines, in clause order, the
+ * clauses where its literal is false); then each remaining variable in
+ * priority order that is still unassigned takes its sampled value and is
+ * propagated.  A clause is the set of its distinct literals; 0 entries are
+ * the clause's first literal.  threads: host threads (0 = all cores),
+ * chains are independent.  Allocates host memory only; no GPU call. */
+hp_status hp_unit_propagate(const hp_cnf *cnf, int32_t formula, int32_t n_chains, const uint8_t *v,
+                            const double *nu, uint8_t *out, int32_t threads);
+
+/* Device.  For every formula: counts the clauses satisfied by the current
+ * state->v and by cand_v (DEVICE, the state's [sum N_f * B] layout), stacks
+ * the 2B rows (current first), sorts the counts stably in ascending order
+ * and keeps the last B rows as the new state->v (equal counts favour the
+ * returned rows); a kept row takes the nu of the chain it came from.
+ * s_max, best and t are unchanged.  The plan allocates its staging buffers
+ * on first use.  Stream-ordered; cand_v must stay valid until it is done. */
+hp_status hp_merge_candidates(hp_plan_t plan, const hp_state *state, const uint8_t *cand_v, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,12 +17,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhp.so")
 
-SOURCES = ["hp_host.cpp", "hp_kernels.hip", "hp_mlp.hip"]
+SOURCES = ["hp_host.cpp", "hp_up.cpp", "hp_kernels.hip", "hp_mlp.hip", "hp_merge.hip"]
 HEADERS = ["hp_internal.hpp", "philox.hpp"]
 ARCH = "gfx950"
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
     f"-I{os.path.join(ROOT, 'include')}",

@@ -56,6 +56,10 @@ void release(Plan *p) {
     (void)hipFree(p->d_feat_acc);
     (void)hipFree(p->d_fd);
     (void)hipFree(p->d_work);
+    (void)hipFree(p->d_work_fb);
+    (void)hipFree(p->d_mg_cnt);
+    (void)hipFree(p->d_mg_v);
+    (void)hipFree(p->d_mg_nu);
     (void)hipFree(p->d_lits);
     (void)hipFree(p->d_csr_ptr);
     (void)hipFree(p->d_occ);
@@ -80,7 +84,6 @@ void release(Plan *p) {
     delete p;
 }
 
-size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Variable groups (of 4) per thread whose variance EMA stays in registers:
 // 1 or 2, else 0 (EMA in global memory).  The mixed-precision kernel keeps
@@ -512,6 +515,10 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     } while (0)
     HP_TRY(upload(&p->d_fd, fd, s), "upload formulas");
     HP_TRY(upload(&p->d_work, work, s), "upload work list");
+    std::vector<WorkItem> work_fb((size_t)F * B);
+    for (int f = 0; f < F; ++f)
+        for (int b = 0; b < B; ++b) work_fb[(size_t)f * B + b] = {f, b};
+    HP_TRY(upload(&p->d_work_fb, work_fb, s), "upload work list (formula order)");
     HP_TRY(upload(&p->d_lits, lits, s), "upload clause table");
     HP_TRY(upload(&p->d_csr_ptr, csr_ptr, s), "upload occurrence offsets");
     HP_TRY(upload(&p->d_occ, occ, s), "upload occurrences");
@@ -777,6 +784,18 @@ hp_status hp_init_chains(hp_plan_t plan, const float *q, int32_t chain_lo, int32
     if (chain_lo < 0 || chain_hi > p->B || chain_lo > chain_hi) return fail(HP_EINVAL, "bad chain range");
     hipError_t e = launch_init_chains(*p, q, chain_lo, chain_hi, st->v, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "init chains");
+    return HP_OK;
+}
+
+hp_status hp_merge_candidates(hp_plan_t plan, const hp_state *st, const uint8_t *cand_v, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !st || !cand_v || !st->v || !st->nu) return fail(HP_EINVAL, "null argument");
+    if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B ||
+        st->nu_bytes != (p->precision == HP_FP32 ? 4 : 8))
+        return fail(HP_EINVAL, "state shape does not match the plan");
+    hipError_t e = launch_merge(*p, *st, cand_v, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "merge");
     return HP_OK;
 }
 

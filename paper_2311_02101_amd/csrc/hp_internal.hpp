@@ -175,6 +175,10 @@ struct Plan {
     // device memory
     FormulaDev *d_fd = nullptr;
     WorkItem *d_work = nullptr;
+    WorkItem *d_work_fb = nullptr;        // the same items in (formula, chain) order
+    int32_t *d_mg_cnt = nullptr;          // merge: counts (current, returned), source rows
+    uint8_t *d_mg_v = nullptr;            // merge: staging of v and nu (allocated on first use)
+    unsigned char *d_mg_nu = nullptr;
     uint16_t *d_lits = nullptr;
     uint32_t *d_csr_ptr = nullptr;
     uint32_t *d_occ = nullptr;
@@ -223,6 +227,7 @@ hipError_t launch_weights_to_bf16(const hp_mlp &net, hipStream_t s);
 hipError_t launch_init_chains(const Plan &p, const float *q, int chain_lo, int chain_hi, uint8_t *v,
                               hipStream_t s);
 hipError_t launch_chain_mean(const Plan &p, const uint8_t *a, float *out, hipStream_t s);
+hipError_t launch_merge(Plan &p, const hp_state &st, const uint8_t *cand, hipStream_t s);
 
 void set_error(const std::string &msg);
 

@@ -21,7 +21,7 @@ PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
 KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
 EXPORTS = ("hp_plan", "hp_run", "hp_tune", "hp_check", "hp_plan_query", "hp_free",
-           "hp_status_string", "hp_last_error")
+           "hp_status_string", "hp_last_error", "hp_unit_propagate", "hp_merge_candidates")
 
 
 class HpError(RuntimeError):
@@ -97,8 +97,35 @@ def load():
     lib.hp_status_string.restype = ct.c_char_p
     lib.hp_last_error.argtypes = []
     lib.hp_last_error.restype = ct.c_char_p
+    lib.hp_unit_propagate.argtypes = [ct.POINTER(HpCnf), ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                      ct.c_void_p, ct.c_int32]
+    lib.hp_unit_propagate.restype = ct.c_int
+    lib.hp_merge_candidates.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_void_p, ct.c_void_p]
+    lib.hp_merge_candidates.restype = ct.c_int
     _lib = lib
     return lib
+
+
+def unit_propagate(tables, n_vars, formula, v, nu, threads=0):
+    """Prioritized unit propagation (host, ``hp_unit_propagate``) of the chains
+    of one formula.  tables/n_vars: the formula batch; v: uint8 [B][N_f]; nu:
+    float64 [B][N_f] (host arrays).  Returns the new uint8 [B][N_f]."""
+    lib = load()
+    tables = [np.asarray(t, dtype=np.int32) for t in tables]
+    K = tables[0].shape[0]
+    var_offset = np.concatenate([[0], np.cumsum([int(n) for n in n_vars])]).astype(np.int64)
+    clause_offset = np.concatenate([[0], np.cumsum([t.shape[1] for t in tables])]).astype(np.int64)
+    lits = np.ascontiguousarray(np.concatenate(tables, axis=1), dtype=np.int32)
+    cnf = HpCnf(len(tables), _ptr(var_offset, ct.c_int64), _ptr(clause_offset, ct.c_int64), K,
+                _ptr(lits, ct.c_int32))
+    v = np.ascontiguousarray(v, dtype=np.uint8)
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    if v.shape != nu.shape or v.ndim != 2 or v.shape[1] != int(n_vars[formula]):
+        raise ValueError("v and nu must be [B][N_f] of the formula")
+    out = np.empty_like(v)
+    _check(lib.hp_unit_propagate(ct.byref(cnf), int(formula), v.shape[0], v.ctypes.data, nu.ctypes.data,
+                                 out.ctypes.data, int(threads)))
+    return out
 
 
 def device_available() -> bool:
@@ -205,6 +232,12 @@ class Plan:
     def check(self):
         """Synchronise and raise if a device-side barrier timed out."""
         _check(load().hp_check(self._h))
+
+    def merge_candidates(self, state, cand_v, stream=None):
+        """Top-B merge (``hp_merge_candidates``) of candidate assignments
+        (device uint8 tensor in the state's layout) into ``state``."""
+        _check(load().hp_merge_candidates(self._h, ct.byref(state.c_struct()), ct.c_void_p(cand_v.data_ptr()),
+                                          _stream_handle(stream)))
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,0 +1,143 @@
+"""Sampling with the periodic unit-propagation exchange (Sec. 3.4; the
+appendix program's exchange).
+
+Every ``upp`` sweeps the chains' (v, nu) are copied to pinned host memory;
+host threads run the prioritized unit propagation (``hp_unit_propagate``) on
+every formula while the GPU samples ``upw`` more sweeps; then the returned
+assignments are merged on the device (``hp_merge_candidates``: stack under the
+current states, count, keep the best B per formula).  The GPU never waits for
+the host except at the merge, which needs the host's result.
+
+    python -m paper_2311_02101_amd.solver [--workload NAME] [--sweeps S] [--upp P] [--upw W]
+
+runs the same workload with and without the exchange (same seeds) and prints
+the best satisfied-clause counts and the timings as one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import threading
+import time
+
+import numpy as np
+
+from . import hp
+from . import workload as wl
+
+
+def _host_views(plan, host_v, host_nu):
+    """Per-formula [B][N_f] numpy views of flat host buffers (state layout)."""
+    out = []
+    for f in range(plan.F):
+        lo, hi = int(plan.var_offset[f]) * plan.B, int(plan.var_offset[f + 1]) * plan.B
+        n = plan.n_vars[f]
+        out.append((host_v[lo:hi].reshape(plan.B, n), host_nu[lo:hi].reshape(plan.B, n)))
+    return out
+
+
+def solve(plan, tables, state, sweeps, upp, upw, threads=0, stream=None):
+    """Advance ``state`` by ``sweeps`` sweeps with an exchange every ``upp``
+    sweeps whose result is merged ``upw`` sweeps later (0 < upw < upp).
+    Returns statistics (exchanges, host seconds, merge seconds)."""
+    import torch
+    if not (0 < upw < upp):
+        raise ValueError("need 0 < upw < upp")
+    stream = torch.cuda.current_stream() if stream is None else stream
+    host_v = torch.empty(state.v.shape, dtype=torch.uint8, pin_memory=True)
+    host_nu = torch.empty(state.nu.shape, dtype=state.nu.dtype, pin_memory=True)
+    cand_host = torch.empty(state.v.shape, dtype=torch.uint8, pin_memory=True)
+    cand = torch.empty_like(state.v)
+    views = _host_views(plan, host_v.numpy(), host_nu.numpy())
+    cand_views = _host_views(plan, cand_host.numpy(), host_nu.numpy())
+    stats = {"exchanges": 0, "host_s": 0.0, "wait_s": 0.0}
+    t = 0
+    next_send = upp
+    while t < sweeps:
+        run_to = min(next_send, sweeps)
+        plan.run(state, run_to - t, stream)
+        t = run_to
+        if t < next_send:
+            break
+        next_send += upp
+        if t + upw > sweeps:
+            continue
+        # send: snapshot (v, nu) into pinned memory, propagate on host threads
+        with torch.cuda.stream(stream):
+            host_v.copy_(state.v, non_blocking=True)
+            host_nu.copy_(state.nu, non_blocking=True)
+        ready = torch.cuda.Event()
+        ready.record(stream)
+        err = []
+
+        def work():
+            try:
+                t0 = time.perf_counter()
+                ready.synchronize()
+                for f, (v, nu) in enumerate(views):
+                    cand_views[f][0][...] = hp.unit_propagate(tables, plan.n_vars, f, v,
+                                                              nu.astype(np.float64), threads)
+                stats["host_s"] += time.perf_counter() - t0
+            except Exception as e:          # re-raised on the caller's thread
+                err.append(e)
+
+        th = threading.Thread(target=work)
+        th.start()
+        plan.run(state, upw, stream)        # the GPU keeps sampling meanwhile
+        t += upw
+        t0 = time.perf_counter()
+        th.join()
+        stats["wait_s"] += time.perf_counter() - t0
+        if err:
+            raise err[0]
+        with torch.cuda.stream(stream):
+            cand.copy_(cand_host, non_blocking=True)
+        plan.merge_candidates(state, cand, stream)
+        stats["exchanges"] += 1
+    return stats
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="plain_n4096_b64")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "mixed"])
+    ap.add_argument("--sweeps", type=int, default=5000)
+    ap.add_argument("--upp", type=int, default=500)
+    ap.add_argument("--upw", type=int, default=100)
+    ap.add_argument("--threads", type=int, default=16)
+    ap.add_argument("--formulas", type=int, default=0, help="limit a batch workload to its first formulas")
+    args = ap.parse_args(argv)
+    w = wl.config_workload(args.workload, precision=args.precision)
+    tables, n_vars, v0 = w.tables, w.n_vars, w.v0
+    if args.formulas:
+        tables, n_vars, v0 = tables[:args.formulas], n_vars[:args.formulas], v0[:args.formulas]
+    out = {"workload": args.workload, "sweeps": args.sweeps, "upp": args.upp, "upw": args.upw,
+           "chains": w.chains, "formulas": len(tables)}
+    for use_up in (False, True):
+        plan = hp.Plan(tables, n_vars, w.W, w.b, chains=w.chains, temps=w.temps, precision=args.precision,
+                       alpha=w.alpha, seed=w.seed)
+        st = plan.new_state(v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if use_up:
+            stats = solve(plan, tables, st, args.sweeps, args.upp, args.upw, args.threads)
+        else:
+            plan.run(st, args.sweeps)
+            stats = {}
+        plan.run(st, 0)                     # count the final states too
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        best = [int(st.formula(f)[2].max()) for f in range(len(tables))]
+        key = "with_up" if use_up else "plain"
+        out[key] = {"best_mean": float(np.mean(best)), "best": best[:8], "seconds": wall, **stats}
+        print(f"[solver] {key}: mean best {np.mean(best):.2f} in {wall:.2f} s", file=sys.stderr, flush=True)
+        plan.free()
+    out["gain_mean"] = out["with_up"]["best_mean"] - out["plain"]["best_mean"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
