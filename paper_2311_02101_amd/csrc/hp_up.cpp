@@ -35,8 +35,8 @@ struct UpFormula {
     std::vector<int32_t> cl_ptr;   // [C+1] into lit
     std::vector<int32_t> lit;      // distinct literals, signed 1-based
     std::vector<int32_t> occ_ptr;  // [N+1] into occ
-    std::vector<int32_t> occ;      // clause indices per variable, clause order,
-                                   // once per distinct literal of the variable
+    std::vector<int32_t> occ;      // per variable, in clause order, once per
+                                   // distinct literal: clause << 1 | negated
 };
 
 // Builds the clause and occurrence lists of formula f; false on a bad table.
@@ -83,7 +83,8 @@ bool build_formula(const hp_cnf *cnf, int f, UpFormula &F, std::string &err) {
     std::vector<int32_t> fill(F.occ_ptr.begin(), F.occ_ptr.end() - 1);
     const int32_t C = (int32_t)(F.cl_ptr.size() - 1);
     for (int32_t c = 0; c < C; ++c)
-        for (int32_t j = F.cl_ptr[c]; j < F.cl_ptr[c + 1]; ++j) F.occ[fill[std::abs(F.lit[j]) - 1]++] = c;
+        for (int32_t j = F.cl_ptr[c]; j < F.cl_ptr[c + 1]; ++j)
+            F.occ[fill[std::abs(F.lit[j]) - 1]++] = (c << 1) | (F.lit[j] < 0 ? 1 : 0);
     return true;
 }
 
@@ -129,13 +130,12 @@ void up_chain(const UpFormula &F, const uint8_t *v, const double *nu, uint8_t *o
     auto propagate = [&]() {
         while (head < w.queue.size()) {
             const int32_t i = w.queue[head++];
-            for (int32_t j = F.occ_ptr[i]; j < F.occ_ptr[i + 1]; ++j) {
-                const int32_t c = F.occ[j];
-                bool is_false = false;
-                for (int32_t q = F.cl_ptr[c]; q < F.cl_ptr[c + 1]; ++q)
-                    if (std::abs(F.lit[q]) - 1 == i && lit_value(w.val, F.lit[q]) == 0) is_false = true;
-                if (is_false) examine(c);
-            }
+            // clauses in which the literal of i is false: the positive ones
+            // when i = 0, the negated ones when i = 1 (a clause holding both
+            // literals is examined once, from the false one, and is satisfied)
+            const int32_t false_neg = w.val[i];
+            for (int32_t j = F.occ_ptr[i]; j < F.occ_ptr[i + 1]; ++j)
+                if ((F.occ[j] & 1) == false_neg) examine(F.occ[j] >> 1);
         }
     };
     const int32_t half = n / 2;

@@ -114,27 +114,34 @@ def main(argv=None):
     if args.formulas:
         tables, n_vars, v0 = tables[:args.formulas], n_vars[:args.formulas], v0[:args.formulas]
     out = {"workload": args.workload, "sweeps": args.sweeps, "upp": args.upp, "upw": args.upw,
-           "chains": w.chains, "formulas": len(tables)}
-    for use_up in (False, True):
+           "chains": w.chains, "formulas": len(tables), "host_threads": args.threads}
+
+    def run(use_up, sweeps):
         plan = hp.Plan(tables, n_vars, w.W, w.b, chains=w.chains, temps=w.temps, precision=args.precision,
                        alpha=w.alpha, seed=w.seed)
         st = plan.new_state(v0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if use_up:
-            stats = solve(plan, tables, st, args.sweeps, args.upp, args.upw, args.threads)
-        else:
-            plan.run(st, args.sweeps)
-            stats = {}
+        stats = solve(plan, tables, st, sweeps, args.upp, args.upw, args.threads) if use_up else {}
+        if not use_up:
+            plan.run(st, sweeps)
         plan.run(st, 0)                     # count the final states too
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         best = [int(st.formula(f)[2].max()) for f in range(len(tables))]
-        key = "with_up" if use_up else "plain"
-        out[key] = {"best_mean": float(np.mean(best)), "best": best[:8], "seconds": wall, **stats}
-        print(f"[solver] {key}: mean best {np.mean(best):.2f} in {wall:.2f} s", file=sys.stderr, flush=True)
         plan.free()
-    out["gain_mean"] = out["with_up"]["best_mean"] - out["plain"]["best_mean"]
+        return {"sweeps": sweeps, "best_mean": float(np.mean(best)), "best": best[:8], "seconds": wall, **stats}
+
+    out["plain"] = run(False, args.sweeps)
+    out["with_up"] = run(True, args.sweeps)
+    # the plain method given the same wall time as the run with the exchange
+    eq = int(round(args.sweeps * out["with_up"]["seconds"] / out["plain"]["seconds"]))
+    out["plain_equal_time"] = run(False, max(eq, args.sweeps))
+    out["gain_equal_sweeps"] = out["with_up"]["best_mean"] - out["plain"]["best_mean"]
+    out["gain_equal_time"] = out["with_up"]["best_mean"] - out["plain_equal_time"]["best_mean"]
+    for k in ("plain", "with_up", "plain_equal_time"):
+        print(f"[solver] {k}: {out[k]['sweeps']} sweeps, mean best {out[k]['best_mean']:.2f} "
+              f"in {out[k]['seconds']:.3f} s", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     return 0
 
