@@ -88,8 +88,9 @@ typedef struct {
 
 typedef struct {
     int32_t chains;                 /* B chains per formula (the "batch size"), >= 1   */
-    const int32_t *temp_of_chain;   /* host [B] temperature index per chain, or NULL:
-                                       chain b uses floor(b*n_temps/B)                 */
+    const int32_t *temp_of_chain;   /* host [B] initial temperature index of chain b of
+                                       every formula, or NULL: floor(b*n_temps/B);
+                                       hp_temper changes them per formula             */
     int32_t precision;              /* hp_precision                                    */
     double alpha;                   /* variance moving-average rate, in [0, 1]         */
     uint64_t seed;                  /* Philox key source                               */
@@ -285,6 +286,25 @@ hp_status hp_unit_propagate(const hp_cnf *cnf, int32_t formula, int32_t n_chains
  * s_max, best and t are unchanged.  The plan allocates its staging buffers
  * on first use.  Stream-ordered; cand_v must stay valid until it is done. */
 hp_status hp_merge_candidates(hp_plan_t plan, const hp_state *state, const uint8_t *cand_v, void *stream);
+
+/* ---- Replica exchange across the temperatures -----------------------------
+ * Chains at temperature tau sample p_tau(v) ~ exp(-F_tau(v)), F_tau the
+ * formula free energy (eq. 5: sum over clauses of the clause free energy,
+ * eq. 1, of the clause's literal values, eq. 4).  One round, for every
+ * formula: the pairs (tau, tau+1) with tau of the given parity pair the k-th
+ * chain (by chain index) at tau with the k-th chain at tau + 1; a pair (a, b)
+ * exchanges temperatures iff U < exp(min(D, 0)),
+ *   D = F_tau(v_a) + F_tau+1(v_b) - F_tau(v_b) - F_tau+1(v_a),
+ * U = (w >> 8) 2^-24, w = word 0 of the sweep generator's Philox at counter
+ * (t mod 2^32, a, 2^31 - 1, t div 2^32) with t = *state->t (device).  The
+ * plan's temperature of every (formula, chain) changes; v, nu, s_max, best
+ * and t do not.  Up to 16 temperatures.  The plan allocates its workspace on
+ * first use.  Stream-ordered. */
+hp_status hp_temper(hp_plan_t plan, const hp_state *state, int32_t parity, void *stream);
+
+/* Copies the plan's temperatures, HOST [n_formulas][chains] int32, and waits
+ * for the copy on `stream`. */
+hp_status hp_get_temps(hp_plan_t plan, int32_t *out, void *stream);
 
 #ifdef __cplusplus
 }

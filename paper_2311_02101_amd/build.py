@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhp.so")
 
-SOURCES = ["hp_host.cpp", "hp_up.cpp", "hp_kernels.hip", "hp_mlp.hip", "hp_merge.hip"]
+SOURCES = ["hp_host.cpp", "hp_up.cpp", "hp_kernels.hip", "hp_mlp.hip", "hp_merge.hip", "hp_temper.hip"]
 HEADERS = ["hp_internal.hpp", "philox.hpp"]
 ARCH = "gfx950"
 

@@ -75,6 +75,9 @@ void release(Plan *p) {
     (void)hipFree(p->d_bar);
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_temp);
+    (void)hipFree(p->d_fe);
+    (void)hipFree(p->d_fe_chain);
+    (void)hipFree(p->d_temp_old);
     (void)hipFree(p->d_W);
     (void)hipFree(p->d_b);
     (void)hipFree(p->tab.thr);
@@ -229,10 +232,12 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
     for (int i = 0; i < T * L; ++i)
         if (!std::isfinite(rbm->b[i])) return fail(HP_EINVAL, "non-finite bias");
-    std::vector<int32_t> temp(B);
+    // temperature of every (formula, chain); replica exchange changes them per formula
+    std::vector<int32_t> temp((size_t)F * B);
     for (int b = 0; b < B; ++b) {
-        temp[b] = opts->temp_of_chain ? opts->temp_of_chain[b] : (int32_t)((int64_t)b * T / B);
-        if (temp[b] < 0 || temp[b] >= T) return fail(HP_EINVAL, "temperature index out of range");
+        const int32_t t = opts->temp_of_chain ? opts->temp_of_chain[b] : (int32_t)((int64_t)b * T / B);
+        if (t < 0 || t >= T) return fail(HP_EINVAL, "temperature index out of range");
+        for (int f = 0; f < F; ++f) temp[(size_t)f * B + b] = t;
     }
     if (cnf->var_offset[0] != 0 || cnf->clause_offset[0] != 0)
         return fail(HP_EINVAL, "offsets must start at 0");
@@ -796,6 +801,30 @@ hp_status hp_merge_candidates(hp_plan_t plan, const hp_state *st, const uint8_t 
         return fail(HP_EINVAL, "state shape does not match the plan");
     hipError_t e = launch_merge(*p, *st, cand_v, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "merge");
+    return HP_OK;
+}
+
+hp_status hp_temper(hp_plan_t plan, const hp_state *st, int32_t parity, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !st || !st->v || !st->t) return fail(HP_EINVAL, "null argument");
+    if (st->total_vars != p->total_vars || st->n_formulas != p->F || st->chains != p->B)
+        return fail(HP_EINVAL, "state shape does not match the plan");
+    if (parity != 0 && parity != 1) return fail(HP_EINVAL, "parity must be 0 or 1");
+    if (p->T > kMaxTemperTemps) return fail(HP_EUNSUPPORTED, "replica exchange handles up to 16 temperatures");
+    hipError_t e = launch_temper(*p, *st, parity, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "replica exchange");
+    return HP_OK;
+}
+
+hp_status hp_get_temps(hp_plan_t plan, int32_t *out, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !out) return fail(HP_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(out, p->d_temp, (size_t)p->F * p->B * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "read temperatures");
     return HP_OK;
 }
 

@@ -90,7 +90,7 @@ struct SweepParams {
     const int64_t *gfx;          // [T][256][8]
     const int64_t *gpad;         // [T][8][256]
     const uint4 *mfma;           // [T][2][64] mixed-precision A operands
-    const int32_t *temp_of_chain;
+    const int32_t *temp_of_chain;  // [F][B] temperature index per (formula, chain)
     uint8_t *v;
     Real *nu;
     int32_t *s_max;
@@ -186,7 +186,10 @@ struct Plan {
     uint32_t *d_orig = nullptr;
     int32_t *d_negcnt = nullptr;
     int32_t *d_tabflag = nullptr;
-    int32_t *d_temp = nullptr;
+    int32_t *d_temp = nullptr;            // [F][B]
+    double *d_fe = nullptr;               // replica exchange: [T][128] clause free energies,
+    double *d_fe_chain = nullptr;         //   [F][B][T] formula free energies,
+    int32_t *d_temp_old = nullptr;        //   [F][B] temperatures before the round
     double *d_W = nullptr;
     double *d_b = nullptr;
     DeviceTables tab;
@@ -228,6 +231,8 @@ hipError_t launch_init_chains(const Plan &p, const float *q, int chain_lo, int c
                               hipStream_t s);
 hipError_t launch_chain_mean(const Plan &p, const uint8_t *a, float *out, hipStream_t s);
 hipError_t launch_merge(Plan &p, const hp_state &st, const uint8_t *cand, hipStream_t s);
+constexpr int kMaxTemperTemps = 16;
+hipError_t launch_temper(Plan &p, const hp_state &st, int parity, hipStream_t s);
 
 void set_error(const std::string &msg);
 

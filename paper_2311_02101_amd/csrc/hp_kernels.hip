@@ -200,7 +200,7 @@ __global__ __launch_bounds__(1024) void sweep_pull_kernel(SweepParams<Real> P) {
     const FormulaDev fd = P.fd[w.f];
     const int N = fd.n, C = fd.c;
     const int tid = threadIdx.x, NT = blockDim.x;
-    const int tau = P.temp_of_chain[w.b];
+    const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
     const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
     const uint16_t *__restrict__ lits = P.lits + fd.clause_off;
     const uint32_t *__restrict__ cptr = P.csr_ptr + fd.ptr_off;
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         const WorkItem w = P.work[item];
         const FormulaDev fd = P.fd[w.f];
         const int N = fd.n, C = fd.c;
-        const int tau = P.temp_of_chain[w.b];
+        const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
         const PushLds L = kWide ? push_lds_wide(lds, P.lds_x_off, P.lds_v_off, P.gfx, P.gpad, tau)
                                 : push_lds(lds, P.lds_x_off, P.lds_v_off);
         const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
@@ -918,7 +918,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     const FormulaDev fd = P.fd[w.f];
     const int N = fd.n;
     const int tid = threadIdx.x, NT = blockDim.x;
-    const int tau = P.temp_of_chain[w.b];
+    const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
     c.G = G;
     c.g = g;
     c.N = N;

@@ -21,7 +21,8 @@ PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
 KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
 EXPORTS = ("hp_plan", "hp_run", "hp_tune", "hp_check", "hp_plan_query", "hp_free",
-           "hp_status_string", "hp_last_error", "hp_unit_propagate", "hp_merge_candidates")
+           "hp_status_string", "hp_last_error", "hp_unit_propagate", "hp_merge_candidates", "hp_temper",
+           "hp_get_temps")
 
 
 class HpError(RuntimeError):
@@ -102,6 +103,10 @@ def load():
     lib.hp_unit_propagate.restype = ct.c_int
     lib.hp_merge_candidates.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_void_p, ct.c_void_p]
     lib.hp_merge_candidates.restype = ct.c_int
+    lib.hp_temper.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int32, ct.c_void_p]
+    lib.hp_temper.restype = ct.c_int
+    lib.hp_get_temps.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.hp_get_temps.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -232,6 +237,16 @@ class Plan:
     def check(self):
         """Synchronise and raise if a device-side barrier timed out."""
         _check(load().hp_check(self._h))
+
+    def temper(self, state, parity, stream=None):
+        """One replica-exchange round (``hp_temper``) on the pairs of one parity."""
+        _check(load().hp_temper(self._h, ct.byref(state.c_struct()), int(parity), _stream_handle(stream)))
+
+    def current_temps(self, stream=None):
+        """Current temperature of every (formula, chain): int32 [F][B]."""
+        out = np.empty((self.F, self.B), np.int32)
+        _check(load().hp_get_temps(self._h, out.ctypes.data, _stream_handle(stream)))
+        return out
 
     def merge_candidates(self, state, cand_v, stream=None):
         """Top-B merge (``hp_merge_candidates``) of candidate assignments
