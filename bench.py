@@ -1,6 +1,7 @@
 """Benchmark of the block-Gibbs hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--precision f64|f32] [--workload NAME]
+                    [--model padded|clustered]
 
 Default workload: the formula N = 4096, C = 24576 (K = 7, L = 8) with its 64
 chains.  One step advances every formula of the workload 500 sweeps on all
@@ -48,6 +49,30 @@ def chain_sweep_work(n_vars, n_clauses, L):
     return calls, draws, calls * PHILOX_SLOTS + draws * DRAW_SLOTS
 
 
+def clause_lengths(table):
+    """Length of every clause of a padded [K][C] table: K minus the trailing
+    copies of its first literal."""
+    t = np.asarray(table)
+    same = t == t[:1]
+    k = t.shape[0]
+    lens = np.full(t.shape[1], k)
+    for j in range(k - 1, 0, -1):
+        run = np.all(same[j:], axis=0)
+        lens = np.where(run, j, lens)
+    return lens
+
+
+def chain_sweep_work_clustered(n_vars, table):
+    """The same model for the size-clustered formula-RBM: a clause of length
+    len draws L = 3 hidden units (one Philox call) when len <= 3, else len + 1
+    units (two calls)."""
+    lens = clause_lengths(table)
+    big = lens > 3
+    calls = int(np.sum(np.where(big, 2, 1))) + -(-n_vars // 4)
+    draws = int(np.sum(np.where(big, lens + 1, 3))) + n_vars
+    return calls, draws, calls * PHILOX_SLOTS + draws * DRAW_SLOTS
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +88,8 @@ def main(argv=None):
                     help="sweeps of the oracle sample (all chains); 0 skips the CPU leg")
     ap.add_argument("--graph", type=int, default=-1, help="hipGraph replay (default: on for batches)")
     ap.add_argument("--tune", type=int, default=-1, help="autotune first (default: on for batches)")
+    ap.add_argument("--model", default="padded", choices=["padded", "clustered"],
+                    help="padded formula-RBM (K = 7, L = 8 for every clause) or the size-clustered one")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run y = -x over this many MiB (a plain streaming kernel whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters), then exit")
@@ -99,9 +126,11 @@ def main(argv=None):
     L = w.W.shape[2]
     batch = len(w.n_vars) > 1
     use_graph = (args.graph if args.graph >= 0 else int(batch)) == 1
+    clustered = args.model == "clustered"
+    w.size_rbms = wl.pretrained_size_rbms() if clustered else None
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=B, temps=w.temps,
                    precision=args.precision, alpha=w.alpha, seed=w.seed, threads=args.threads,
-                   kernel=args.kernel, split=args.split, graph=use_graph)
+                   kernel=args.kernel, split=args.split, graph=use_graph, size_rbms=w.size_rbms)
     progress(f"planned: {plan.info()['n_buckets']} launch(es)")
     if (args.tune if args.tune >= 0 else int(batch)) == 1:
         plan.tune(n_sweeps=3)
@@ -132,7 +161,7 @@ def main(argv=None):
     value = instances / wall
     calls = draws = slots = 0
     for n, t in zip(w.n_vars, w.tables):
-        c1, d1, s1 = chain_sweep_work(n, t.shape[1], L)
+        c1, d1, s1 = chain_sweep_work_clustered(n, t) if clustered else chain_sweep_work(n, t.shape[1], L)
         calls, draws, slots = calls + c1, draws + d1, slots + s1
     per_launch_slots = slots * B * args.sweeps
     achieved = per_launch_slots / avg_launch_s
@@ -149,8 +178,8 @@ def main(argv=None):
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": args.workload, "formulas": len(w.n_vars),
-                   "n_vars": N, "clauses": C, "K": 7, "L": L,
+        "config": {"workload": args.workload, "formulas": len(w.n_vars), "model": args.model,
+                   "n_vars": N, "clauses": C, "K": 7, "L": L if not clustered else "3 or len + 1",
                    "chains": B, "sweeps_per_step": args.sweeps, "temperatures": list(wl.FSTAR_PAIR),
                    "graph": use_graph,
                    "threads": plan_threads(args.threads), "kernel": args.kernel,
@@ -213,6 +242,7 @@ def cpu_baseline(w, plan, sweeps, precision, dev):
     The rate is scaled to instances/s of the whole workload by its total
     chain-sweep work, weighted by formula size."""
     import torch
+    from oracle import clustered as CL
     from oracle import rbmsat as R
 
     batch = len(w.n_vars) > 1
@@ -229,11 +259,15 @@ def cpu_baseline(w, plan, sweeps, precision, dev):
     plan.run(st, sw)
     torch.cuda.synchronize()
     for f in pick:
-        op = R.plan(w.tables[f], w.n_vars[f], w.W, w.b)
         ost = R.initial(w.v0[f][chains])
         t0 = time.perf_counter()
-        R.run(ost, op, w.temps[chains], sw, alpha=w.alpha, seed=w.seed, formula_id=f,
-              chain_ids=chains)
+        if w.size_rbms is not None:
+            cp = CL.ClusteredPlan(w.tables[f], w.n_vars[f], w.size_rbms)
+            CL.run(ost, cp, w.temps[chains], sw, alpha=w.alpha, seed=w.seed, formula_id=f, chain_ids=chains)
+        else:
+            op = R.plan(w.tables[f], w.n_vars[f], w.W, w.b)
+            R.run(ost, op, w.temps[chains], sw, alpha=w.alpha, seed=w.seed, formula_id=f,
+                  chain_ids=chains)
         el += time.perf_counter() - t0
         work_done += len(chains) * sw * w.n_vars[f]
         v, nu, s_max, best = st.formula(f)

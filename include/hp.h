@@ -107,6 +107,16 @@ typedef struct {
     int32_t graph;                  /* 1: hp_run replays a captured hipGraph of its
                                        launches (cached per state buffers and sweep
                                        count); incompatible with split > 1           */
+    const hp_rbm *size_rbms;        /* NULL: every clause uses `rbm` (padded to K).
+                                       Else the size-clustered model (Sec. 4): host
+                                       [5] canonical RBMs for K = 3..7 (k = 3+i,
+                                       l = 3 for K = 3 else K+1, n_temps as `rbm`);
+                                       a clause of length l (its column without the
+                                       trailing copies of its first literal) uses
+                                       the K = max(l, 3) RBM, lengths 1..2 padded by
+                                       the first literal; hidden unit j of clause c
+                                       draws block 2c + j/4.  Push launches only (no
+                                       pull kernel, no mixed precision).            */
 } hp_opts;
 
 typedef enum {

@@ -99,18 +99,20 @@ def sweep(st: State, cp: ClusteredPlan, temps, *, alpha: float, seed: int, formu
     st.best[better] = st.v[better]
     u8 = uniforms(seed, formula_id, t, chain_ids, HIDDEN, pf.C, 8)      # [B][C][8], blocks 2c, 2c+1
     x = np.zeros((B, pf.n_vars))
+    hid_margin = np.inf
     for tau in np.unique(temps):
         sel = np.nonzero(temps == tau)[0]
         ph = hidden_probabilities(g[sel], cp, tau)
-        hs = [(np.transpose(u8[sel][:, cs, :Lg], (0, 2, 1)) < p).astype(np.float64)
-              for (Kg, Lg, cs, sp), p in zip(cp.groups, ph)]
+        us = [np.transpose(u8[sel][:, cs, :Lg], (0, 2, 1)) for (Kg, Lg, cs, sp) in cp.groups]
+        hs = [(u < p).astype(np.float64) for u, p in zip(us, ph)]
+        hid_margin = min([hid_margin] + [float(np.abs(u - p).min()) for u, p in zip(us, ph)])
         x[sel] = visible_logits(hs, cp, tau)
     rho = sigmoid(x)
     st.nu = (1 - alpha) * st.nu + alpha * rho * (1 - rho)
     u_v = visible_uniforms(seed, formula_id, t, chain_ids, pf.n_vars)
     st.v = (u_v < rho).astype(np.uint8)
     st.t = t + 1
-    return dict(x=x, rho=rho, u_v=u_v)
+    return dict(x=x, rho=rho, u_v=u_v, hid_margin=hid_margin)
 
 
 def run(st: State, cp: ClusteredPlan, temps, n_sweeps, *, alpha, seed, formula_id=0, chain_ids=None):

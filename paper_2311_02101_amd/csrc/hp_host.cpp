@@ -80,6 +80,8 @@ void release(Plan *p) {
     (void)hipFree(p->d_temp_old);
     (void)hipFree(p->d_W);
     (void)hipFree(p->d_b);
+    (void)hipFree(p->d_Wc);
+    (void)hipFree(p->d_bc);
     (void)hipFree(p->tab.thr);
     (void)hipFree(p->tab.g64);
     (void)hipFree(p->tab.g32);
@@ -232,6 +234,25 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
     for (int i = 0; i < T * L; ++i)
         if (!std::isfinite(rbm->b[i])) return fail(HP_EINVAL, "non-finite bias");
+    // size-clustered model: the RBMs of the groups K = 3 .. max(K, 3)
+    const bool clust = opts->size_rbms != nullptr;
+    const int n_groups = clust ? std::max(K, 3) - 2 : 0;
+    if (clust) {
+        if (opts->precision == HP_MIXED_BF16 || opts->kernel == HP_KERNEL_PULL)
+            return fail(HP_EUNSUPPORTED, "the size-clustered model runs the push launch in FP64 or FP32 only");
+        for (int i = 0; i < n_groups; ++i) {
+            const hp_rbm &r = opts->size_rbms[i];
+            const int Kg = 3 + i;
+            if (r.k != Kg || r.l != clust_hidden(Kg) || r.n_temps != T || !r.W || !r.b)
+                return fail(HP_EINVAL, "size_rbms[" + std::to_string(i) + "] must be the K = " + std::to_string(Kg) +
+                                           " RBM with L = " + std::to_string(clust_hidden(Kg)) +
+                                           " and the plan's n_temps");
+            for (int j = 0; j < T * Kg * r.l; ++j)
+                if (!std::isfinite(r.W[j])) return fail(HP_EINVAL, "non-finite weight in size_rbms");
+            for (int j = 0; j < T * r.l; ++j)
+                if (!std::isfinite(r.b[j])) return fail(HP_EINVAL, "non-finite bias in size_rbms");
+        }
+    }
     // temperature of every (formula, chain); replica exchange changes them per formula
     std::vector<int32_t> temp((size_t)F * B);
     for (int b = 0; b < B; ++b) {
@@ -345,6 +366,15 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     // below 2^62 when (bound + 1) * 2^S < 2^62
     double wsum = 0.0;
     for (int t = 0; t < T; ++t) {
+        if (clust) {
+            for (int i = 0; i < n_groups; ++i) {
+                const int KL = (3 + i) * opts->size_rbms[i].l;
+                double s = 0.0;
+                for (int j = 0; j < KL; ++j) s += std::fabs(opts->size_rbms[i].W[(size_t)t * KL + j]);
+                wsum = std::max(wsum, s);
+            }
+            continue;
+        }
         double s = 0.0;
         for (int i = 0; i < K * L; ++i) s += std::fabs(rbm->W[(size_t)t * K * L + i]);
         wsum = std::max(wsum, s);
@@ -374,6 +404,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     p->total_vars = NV; p->total_clauses = NC; p->total_occ = (int64_t)K * NC;
     p->max_n = max_n; p->max_c = max_c;
     p->fx_shift = fx_shift;
+    p->clust = clust ? 1 : 0;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipGetDevice"); }
     int max_lds = 0;
@@ -393,6 +424,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         const bool fx_ok = fx_shift >= 40;
         if (mixed)   // contributions come from MFMA: only the threshold table in LDS
             return fx_ok && lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds ? kBucketWide : -1;
+        if (clust)   // clustered tables in LDS only
+            return fx_ok && lds_bytes_clust(fd[f].n, &vo, &xo) <= (size_t)max_lds ? kBucketPush : -1;
         if (opts->kernel != HP_KERNEL_PULL && fx_ok) {
             if (lds_bytes_push(fd[f].n, false, &vo, &xo) <= (size_t)max_lds) return kBucketPush;
             if (lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds) return kBucketWide;
@@ -452,6 +485,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     for (Bucket &bk : p->buckets) {
         if (bk.kind == kBucketPull)
             bk.lds = lds_bytes_pull(bk.max_n, bk.max_c, real_bytes, &bk.v_off, &bk.hm_off);
+        else if (clust)
+            bk.lds = lds_bytes_clust(bk.max_n, &bk.v_off, &bk.x_off);
         else
             bk.lds = lds_bytes_push(bk.max_n, bk.kind == kBucketWide, &bk.v_off, &bk.x_off);
         // default workgroup size: about six clauses per thread per sweep
@@ -537,11 +572,33 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(upload(&p->d_clause_off, coff, s), "upload clause offsets");
     HP_TRY(upload(&p->d_W, Wv, s), "upload W_c");
     HP_TRY(upload(&p->d_b, bv, s), "upload b_c");
-    HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kPatterns * kMaxL * sizeof(uint32_t)), "alloc thr");
-    HP_TRY(hipMalloc((void **)&p->tab.g64, (size_t)T * kHidMasks * kMaxL * sizeof(double)), "alloc g64");
-    HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
-    HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kMaxL * sizeof(int64_t)), "alloc gfx");
-    HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kMaxL * kHidMasks * sizeof(int64_t)), "alloc gpad");
+    if (clust) {
+        // the size RBMs back to back; thr / gfx / gpad in the clustered layout
+        std::vector<double> Wc, bc;
+        std::vector<size_t> wo(n_groups), bo(n_groups);
+        for (int i = 0; i < n_groups; ++i) {
+            const hp_rbm &r = opts->size_rbms[i];
+            wo[i] = Wc.size();
+            bo[i] = bc.size();
+            Wc.insert(Wc.end(), r.W, r.W + (size_t)T * r.k * r.l);
+            bc.insert(bc.end(), r.b, r.b + (size_t)T * r.l);
+        }
+        HP_TRY(upload(&p->d_Wc, Wc, s), "upload size RBM weights");
+        HP_TRY(upload(&p->d_bc, bc, s), "upload size RBM biases");
+        for (int i = 0; i < n_groups; ++i) {
+            p->crbm.W[i] = p->d_Wc + wo[i];
+            p->crbm.b[i] = p->d_bc + bo[i];
+        }
+        HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kClustThrRows * kMaxL * sizeof(uint32_t)), "alloc thr");
+        HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kClustGfxRows * kMaxL * sizeof(int64_t)), "alloc gfx");
+        HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kClustGpad * sizeof(int64_t)), "alloc gpad");
+    } else {
+        HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kPatterns * kMaxL * sizeof(uint32_t)), "alloc thr");
+        HP_TRY(hipMalloc((void **)&p->tab.g64, (size_t)T * kHidMasks * kMaxL * sizeof(double)), "alloc g64");
+        HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
+        HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kMaxL * sizeof(int64_t)), "alloc gfx");
+        HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kMaxL * kHidMasks * sizeof(int64_t)), "alloc gpad");
+    }
     if (mixed) {
         std::vector<uint4> ops;
         if (!mfma_operands(rbm->W, rbm->b, T, K, L, ops)) {

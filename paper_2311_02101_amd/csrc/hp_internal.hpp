@@ -66,6 +66,30 @@ struct DeviceTables {
 // four pairs carry 64 bits of every weight.
 constexpr int kLimbs = 8;
 
+// Size-clustered model (Sec. 4): one canonical RBM per clause size K = 3..7
+// with L = 3 hidden units for K = 3 and K + 1 otherwise; a clause of length
+// len uses the RBM of K = max(len, 3), its inputs padded to K by repeating
+// literal 0.  Per temperature the tables of the five groups are concatenated
+// with closed-form offsets:
+//   thr   rows [248][8]  group K at row 2^K - 8           (2^K patterns)
+//   gfx   rows [488][8]  group K at row 0 (K = 3), else 2^(K+1) - 24
+//                                                      (2^L hidden masks)
+//   gpad  [504]          length len at 8 (len - 1) (len <= 3), else
+//                        2^(len+1) - 8                   (2^L masks each)
+// gpad holds the merged contribution of literal 0 and its padding copies
+// (slots len..K-1) of a clause of that length.
+constexpr int kClustGroups = 5;
+constexpr int kClustThrRows = 248;
+constexpr int kClustGfxRows = 488;
+constexpr int kClustGpad = 504;
+__host__ __device__ constexpr int clust_hidden(int K) { return K == 3 ? 3 : K + 1; }
+
+// device pointers of the size RBMs (nullptr for a group no clause uses)
+struct ClustRbm {
+    const double *W[kClustGroups];   // [T][K][L] of K = 3 + i
+    const double *b[kClustGroups];   // [T][L]
+};
+
 // Clause record of the push kernel: 8 x 16-bit slots in a uint4.  Slots
 // 0..6 hold literal k as (0-based variable index) | (negated << 15); slot 7
 // holds len | (negation bits of slots 0..len-1) << 3, where len is the
@@ -162,6 +186,10 @@ struct Plan {
     int32_t xcd_map = 0;
     int64_t nstride = 0;
     int32_t use_graph = 0;
+    int32_t clust = 0;           // size-clustered model: tables in the clustered layout
+    ClustRbm crbm = {};          // its RBMs (device copies in d_Wc / d_bc)
+    double *d_Wc = nullptr;
+    double *d_bc = nullptr;
     int device = 0;
     hipStream_t side[kMaxBuckets] = {};
     hipEvent_t ev_fork = nullptr;
@@ -219,6 +247,7 @@ int split_occupancy(const Plan &p);
 // LDS bytes of the two kernel variants for the largest formula
 size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);
 size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off);
+size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off);
 
 // learned initial assignments (hp_mlp.hip)
 hipError_t launch_features(const Plan &p, float *acc, uint16_t *x, hipStream_t s);

@@ -104,7 +104,59 @@ __global__ void tables_kernel(const double *__restrict__ W, const double *__rest
     }
 }
 
+// Size-clustered tables: one thread per entry of the largest per-temperature
+// table (gfx, 488 x 8); the row offsets are the closed forms of the layout.
+__global__ void clust_tables_kernel(ClustRbm R, int T, int S, uint32_t *__restrict__ thr,
+                                    int64_t *__restrict__ gfx, int64_t *__restrict__ gpad,
+                                    int32_t *__restrict__ flag) {
+    constexpr int per = kClustGfxRows * kMaxL;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= T * per) return;
+    const int tau = tid / per, r = tid % per;
+    if (r < kClustThrRows * kMaxL) {
+        const int row = r / kMaxL, l = r % kMaxL;
+        const int K = 31 - __clz(row + 8);                 // row in [2^K - 8, 2^(K+1) - 8)
+        const int L = clust_hidden(K), m = row - ((1 << K) - 8);
+        uint32_t out = 0;
+        if (l < L && R.W[K - 3]) {
+            const double *Wt = R.W[K - 3] + (size_t)tau * K * L;
+            double z = R.b[K - 3][tau * L + l];
+            for (int k = 0; k < K; ++k)
+                if ((m >> k) & 1) z += Wt[k * L + l];
+            const double pr = 1.0 / (1.0 + exp(-z));
+            const uint32_t c = (uint32_t)ceil(pr * 16777216.0);
+            if (c == 0u) *flag = 1;
+            out = c * 256u - 1u;
+        }
+        thr[(size_t)tau * kClustThrRows * kMaxL + r] = out;
+    }
+    {
+        const int row = r / kMaxL, k = r % kMaxL;
+        const int K = row < 8 ? 3 : 30 - __clz(row + 24);  // row in [2^(K+1) - 24, 2^(K+2) - 24)
+        const int L = clust_hidden(K), n = row - (K == 3 ? 0 : (2 << K) - 24);
+        gfx[(size_t)tau * per + r] = R.W[K - 3] ? g_fixed(R.W[K - 3] + (size_t)tau * K * L, K, L, n, k, S) : 0;
+    }
+    if (r < kClustGpad) {
+        const int len = r < 24 ? r / 8 + 1 : 30 - __clz(r + 8);
+        const int K = len < 3 ? 3 : len, L = clust_hidden(K);
+        const int n = r - (len <= 3 ? 8 * (len - 1) : (2 << len) - 8);
+        int64_t acc = 0;
+        if (R.W[K - 3]) {
+            const double *Wt = R.W[K - 3] + (size_t)tau * K * L;
+            acc = g_fixed(Wt, K, L, n, 0, S);
+            for (int kk = len; kk < K; ++kk) acc += g_fixed(Wt, K, L, n, kk, S);
+        }
+        gpad[(size_t)tau * kClustGpad + r] = acc;
+    }
+}
+
 hipError_t launch_tables(const Plan &p, hipStream_t s) {
+    if (p.clust) {
+        const int n = p.T * kClustGfxRows * kMaxL;
+        clust_tables_kernel<<<(n + 255) / 256, 256, 0, s>>>(p.crbm, p.T, p.fx_shift, p.tab.thr, p.tab.gfx,
+                                                            p.tab.gpad, p.d_tabflag);
+        return hipGetLastError();
+    }
     const int n = p.T * kHidMasks * kMaxL;   // >= the threshold table size
     tables_kernel<<<(n + 255) / 256, 256, 0, s>>>(p.d_W, p.d_b, p.K, p.L, p.T, p.fx_shift, p.tab.thr,
                                                   p.tab.g64, p.tab.g32, p.tab.gfx, p.tab.gpad, p.d_tabflag);
@@ -150,13 +202,26 @@ constexpr int kPushXOff = kPushCntOff + 64 * 4;
 constexpr int kWideCntOff = kPatterns * kMaxL * 4;
 constexpr int kWideXOff = kWideCntOff + 64 * 4;
 
-size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off) {
-    size_t off = wide ? kWideXOff : kPushXOff;
+// size-clustered layout: thr (248 rows) | gfx (488 rows) | gpad (504) | counts | x | v
+constexpr int kClustGfxOff = kClustThrRows * kMaxL * 4;
+constexpr int kClustGpadOff = kClustGfxOff + kClustGfxRows * kMaxL * 8;
+constexpr int kClustCntOff = kClustGpadOff + kClustGpad * 8;
+constexpr int kClustXOff = kClustCntOff + 64 * 4;
+
+static size_t lds_tail(size_t off, int max_n, int32_t *v_off, int32_t *x_off) {
     *x_off = (int32_t)off;
     off += (size_t)max_n * 8;
     *v_off = (int32_t)off;
     off += ((size_t)max_n + 15) / 16 * 16;
     return off;
+}
+
+size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off) {
+    return lds_tail(wide ? kWideXOff : kPushXOff, max_n, v_off, x_off);
+}
+
+size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off) {
+    return lds_tail(kClustXOff, max_n, v_off, x_off);
 }
 
 // Hidden draw of one clause: L Bernoulli bits against the pre-shifted
@@ -352,9 +417,21 @@ __device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, 
                    lds + v_off};
 }
 
-template <bool kWide>
+__device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off, int v_off) {
+    return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kClustGfxOff),
+                   reinterpret_cast<int64_t *>(lds + kClustGpadOff), reinterpret_cast<int *>(lds + kClustCntOff),
+                   reinterpret_cast<int64_t *>(lds + x_off), lds + v_off};
+}
+
+template <bool kWide, bool kClust = false>
 __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_t *thr, const int64_t *gfx,
                                                  const int64_t *gpad, int tau, int tid, int NT) {
+    if (kClust) {
+        for (int i = tid; i < kClustThrRows * kMaxL; i += NT) L.thr[i] = thr[tau * kClustThrRows * kMaxL + i];
+        for (int i = tid; i < kClustGfxRows * kMaxL; i += NT) L.gfx[i] = gfx[tau * kClustGfxRows * kMaxL + i];
+        for (int i = tid; i < kClustGpad; i += NT) L.gpad[i] = gpad[tau * kClustGpad + i];
+        return;
+    }
     for (int i = tid; i < kPatterns * kMaxL; i += NT) L.thr[i] = thr[tau * kPatterns * kMaxL + i];
     if (!kWide) {
         for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
@@ -369,7 +446,11 @@ __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_
 // gather, literal-truth pattern, count; when sampling, the hidden draw and the
 // scatter of the clause's contributions into the LDS accumulators.  Returns
 // this thread's number of satisfied clauses.
-template <bool kSample>
+//
+// kClust: the size-clustered model; a clause of length len takes the tables
+// of group K = max(len, 3) (L = 3 or K + 1 hidden units, drawn from blocks
+// 2c and, for L > 4, 2c + 1), and nbh, full and lmask are unused.
+template <bool kSample, bool kClust = false>
 __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
                                             const uint32_t *__restrict__ orig, int c_first, int c_step,
                                             int c_end, int tid, int NT, uint32_t tlo, uint32_t thi, uint32_t chain,
@@ -402,12 +483,29 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
         if (len > 5) m |= (uint32_t)L.v[e5 & 0x7fffu] << 5;
         if (len > 6) m |= (uint32_t)L.v[e6 & 0x7fffu] << 6;
         m ^= negm;
-        m |= (m & 1u) ? (full & ~((1u << len) - 1u)) : 0u;   // padding copies of literal 0
+        if (kClust) {
+            const uint32_t Kc = len < 3u ? 3u : len;
+            m |= (m & 1u) ? (((1u << Kc) - 1u) & ~((1u << len) - 1u)) : 0u;
+        } else {
+            m |= (m & 1u) ? (full & ~((1u << len) - 1u)) : 0u;   // padding copies of literal 0
+        }
         cnt += (m != 0u);
         if (kSample) {
-            const uint32_t n = hidden_mask(L.thr + m * kMaxL, tlo, thi, chain, oc * nbh, key, nbh) & lmask;
-            push_add(L.x, e0, L.gpad[len * kHidMasks + n]);
-            const int64_t *gr = L.gfx + n * kMaxL;
+            uint32_t n;
+            const int64_t *gr;
+            if (kClust) {
+                const uint32_t Kc = len < 3u ? 3u : len;
+                const bool big = Kc > 3u;                            // L = K + 1 > 4: two blocks
+                n = hidden_mask(L.thr + ((1u << Kc) - 8u + m) * kMaxL, tlo, thi, chain, oc * 2u, key,
+                                big ? 2u : 1u) &
+                    (big ? (2u << Kc) - 1u : 7u);
+                push_add(L.x, e0, L.gpad[(len <= 3u ? 8u * (len - 1u) : (2u << len) - 8u) + n]);
+                gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
+            } else {
+                n = hidden_mask(L.thr + m * kMaxL, tlo, thi, chain, oc * nbh, key, nbh) & lmask;
+                push_add(L.x, e0, L.gpad[len * kHidMasks + n]);
+                gr = L.gfx + n * kMaxL;
+            }
             if (len > 1) push_add(L.x, e1, gr[1]);
             if (len > 2) push_add(L.x, e2, gr[2]);
             if (len > 3) push_add(L.x, e3, gr[3]);
@@ -566,10 +664,10 @@ __device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, i
 // item w.  Otherwise the grid is persistent: workgroups take items from an
 // atomic counter (zeroed before the launch) until all `count` items are done,
 // largest formulas first, so uneven sizes balance over the resident grid.
-template <typename Real, int VPT, bool kWide, bool kMfma = false>
+template <typename Real, int VPT, bool kWide, bool kMfma = false, bool kClust = false>
 __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, uint32_t *queue, int count) {
     extern __shared__ __align__(16) unsigned char lds[];
-    int *s_item = reinterpret_cast<int *>(lds + (kWide ? kWideCntOff : kPushCntOff)) + 63;
+    int *s_item = reinterpret_cast<int *>(lds + (kClust ? kClustCntOff : kWide ? kWideCntOff : kPushCntOff)) + 63;
     const int tid = threadIdx.x, NT = blockDim.x;
     const bool sample = P.n_sweeps > 0;
     const int64_t S = sample ? P.n_sweeps : 1;
@@ -596,15 +694,16 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         const FormulaDev fd = P.fd[w.f];
         const int N = fd.n, C = fd.c;
         const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
-        const PushLds L = kWide ? push_lds_wide(lds, P.lds_x_off, P.lds_v_off, P.gfx, P.gpad, tau)
-                                : push_lds(lds, P.lds_x_off, P.lds_v_off);
+        const PushLds L = kClust ? push_lds_clust(lds, P.lds_x_off, P.lds_v_off)
+                          : kWide ? push_lds_wide(lds, P.lds_x_off, P.lds_v_off, P.gfx, P.gpad, tau)
+                                  : push_lds(lds, P.lds_x_off, P.lds_v_off);
         const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
         const uint4 *__restrict__ rec = P.rec + fd.clause_off;
         const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
         const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
         const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
 
-        load_push_tables<kWide>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+        load_push_tables<kWide, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
         for (int i = tid; i < N; i += NT) {
             L.v[i] = P.v[sbase + i];
             L.x[i] = negcnt[i];
@@ -640,8 +739,10 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
                              : clause_phase_mfma<false>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh,
                                                         full, lmask, P.K, a1, a2, 1.0 / fx_scale);
             else
-                cnt = sample ? clause_phase<true>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask)
-                             : clause_phase<false>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full, lmask);
+                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key,
+                                                          nbh, full, lmask)
+                             : clause_phase<false, kClust>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key,
+                                                           nbh, full, lmask);
             const int total = block_total(L, cnt, tid, NT);
             const bool improved = total > smax;
             if (improved) smax = total;
@@ -782,7 +883,7 @@ struct SplitCtx {
 // sums the G partials of its own variables exactly (integers), draws their new
 // values and publishes them; then every member reads the new values of the
 // groups it does not own.
-template <typename Real, int VPT>
+template <typename Real, int VPT, bool kClust>
 __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const SplitParams &Q, const SplitCtx<Real> &c,
                                              Real (&nu)[VPT > 0 ? VPT : 1][4], int &smax, uint32_t &phase) {
     const PushLds &L = c.L;
@@ -793,10 +894,10 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
         // member g takes every G-th record of the length-sorted order, so all
         // members get the same mix of clause lengths
-        const int cnt = c.sample ? clause_phase<true>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi, (uint32_t)c.b,
-                                                      c.key, c.nbh, c.full, c.lmask)
-                                 : clause_phase<false>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi, (uint32_t)c.b,
-                                                       c.key, c.nbh, c.full, c.lmask);
+        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi,
+                                                              (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask)
+                                 : clause_phase<false, kClust>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi,
+                                                               (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask);
         const int part = block_total(L, cnt, tid, NT);
         // publish the partial logits of the variables other members own
         if (c.sample) {
@@ -894,11 +995,11 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
     }
 }
 
-template <typename Real, int VPT>
+template <typename Real, int VPT, bool kClust = false>
 __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, SplitParams Q) {
     extern __shared__ __align__(16) unsigned char lds[];
     SplitCtx<Real> c;
-    c.L = push_lds(lds, P.lds_x_off, P.lds_v_off);
+    c.L = kClust ? push_lds_clust(lds, P.lds_x_off, P.lds_v_off) : push_lds(lds, P.lds_x_off, P.lds_v_off);
     const PushLds &L = c.L;
 
     // workgroup -> (item, member g); with the XCD map the G members of an
@@ -951,7 +1052,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.ctr = Q.bar + (size_t)item * 32;
     uint32_t phase = 0;
 
-    load_push_tables<false>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+    load_push_tables<false, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
         L.v[i] = P.v[c.sbase + i];
         L.x[i] = 0;
@@ -972,7 +1073,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.t0 = *P.t_ptr;
     __syncthreads();
 
-    split_sweeps<Real, VPT>(P, Q, c, nu, smax, phase);
+    split_sweeps<Real, VPT, kClust>(P, Q, c, nu, smax, phase);
 
     // write back the owned part of the state
     for (int i = c.q_lo * 4 + tid; i < min(N, c.q_hi * 4); i += NT) P.v[c.sbase + i] = L.v[i];
@@ -1014,6 +1115,22 @@ const void *push_kernel_ptr(int vpt, bool wide) {
     }
 }
 
+template <typename Real>
+const void *clust_kernel_ptr(int vpt) {
+    switch (vpt) {
+        case 1: return (const void *)sweep_push_kernel<Real, 1, false, false, true>;
+        case 2: return (const void *)sweep_push_kernel<Real, 2, false, false, true>;
+        default: return (const void *)sweep_push_kernel<Real, 0, false, false, true>;
+    }
+}
+
+template <typename Real>
+const void *split_kernel_ptr(bool clust, int vpt) {
+    if (clust)
+        return vpt == 1 ? (const void *)sweep_split_kernel<Real, 1, true> : (const void *)sweep_split_kernel<Real, 0, true>;
+    return vpt == 1 ? (const void *)sweep_split_kernel<Real, 1> : (const void *)sweep_split_kernel<Real, 0>;
+}
+
 const void *mixed_kernel_ptr(int vpt) {
     switch (vpt) {
         case 1: return (const void *)sweep_push_kernel<double, 1, true, true>;
@@ -1036,7 +1153,9 @@ hipError_t set_limits_t(int bytes) {
     const void *ks[] = {push_kernel_ptr<Real>(1, false), push_kernel_ptr<Real>(2, false), push_kernel_ptr<Real>(0, false),
                         push_kernel_ptr<Real>(1, true),  push_kernel_ptr<Real>(2, true),  push_kernel_ptr<Real>(0, true),
                         pull_kernel_ptr<Real>(1),        pull_kernel_ptr<Real>(2),        pull_kernel_ptr<Real>(0),
-                        (const void *)sweep_split_kernel<Real, 1>, (const void *)sweep_split_kernel<Real, 0>};
+                        clust_kernel_ptr<Real>(1),       clust_kernel_ptr<Real>(2),       clust_kernel_ptr<Real>(0),
+                        split_kernel_ptr<Real>(false, 1), split_kernel_ptr<Real>(false, 0),
+                        split_kernel_ptr<Real>(true, 1),  split_kernel_ptr<Real>(true, 0)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -1058,6 +1177,8 @@ int bucket_occupancy(const Plan &p, const Bucket &b) {
         k = p.precision == HP_FP32 ? pull_kernel_ptr<float>(b.vpt) : pull_kernel_ptr<double>(b.vpt);
     else if (p.precision == HP_MIXED_BF16)
         k = mixed_kernel_ptr(b.vpt);
+    else if (p.clust)
+        k = p.precision == HP_FP64 ? clust_kernel_ptr<double>(b.vpt) : clust_kernel_ptr<float>(b.vpt);
     else
         k = p.precision == HP_FP64 ? push_kernel_ptr<double>(b.vpt, b.kind == kBucketWide)
                                    : push_kernel_ptr<float>(b.vpt, b.kind == kBucketWide);
@@ -1068,20 +1189,20 @@ int bucket_occupancy(const Plan &p, const Bucket &b) {
 
 int split_occupancy(const Plan &p) {
     int nb = 0;
-    const void *kern = p.precision == HP_FP64 ? (const void *)sweep_split_kernel<double, 1>
-                                               : (const void *)sweep_split_kernel<float, 1>;
+    const void *kern = p.precision == HP_FP64 ? split_kernel_ptr<double>(p.clust, 1) : split_kernel_ptr<float>(p.clust, 1);
     const Bucket &b = p.buckets[0];
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, b.threads, b.lds) != hipSuccess) return 0;
     return nb;
 }
 
-template <typename Real, int VPT>
-hipError_t launch_split_one(const Plan &p, SweepParams<Real> P, SplitParams Q, hipStream_t s) {
+template <typename Real>
+hipError_t launch_split_one(const Plan &p, SweepParams<Real> P, SplitParams Q, int vpt, hipStream_t s) {
     const Bucket &b = p.buckets[0];
     // The plan checked that all count*G workgroups fit on the device at once
     // (occupancy x CUs), so on an otherwise idle device they are all resident
     // together; the barrier waits are bounded either way (see hp_check).
-    hipLaunchKernelGGL((sweep_split_kernel<Real, VPT>), dim3(b.count * p.split), dim3(b.threads), b.lds, s, P, Q);
+    hipLaunchKernelGGL((void (*)(SweepParams<Real>, SplitParams))split_kernel_ptr<Real>(p.clust, vpt),
+                       dim3(b.count * p.split), dim3(b.threads), b.lds, s, P, Q);
     return hipGetLastError();
 }
 
@@ -1144,7 +1265,9 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
         if (e != hipSuccess) return e;
         grid = b.grid;
     }
-    const void *kern = p.precision == HP_MIXED_BF16 ? mixed_kernel_ptr(b.vpt) : push_kernel_ptr<Real>(b.vpt, wide);
+    const void *kern = p.precision == HP_MIXED_BF16 ? mixed_kernel_ptr(b.vpt)
+                       : p.clust                     ? clust_kernel_ptr<Real>(b.vpt)
+                                                     : push_kernel_ptr<Real>(b.vpt, wide);
     hipLaunchKernelGGL((void (*)(SweepParams<Real>, uint32_t *, int))kern, dim3(grid), dim3(b.threads), b.lds, s, P,
                        queue, b.count);
     return hipGetLastError();
@@ -1175,7 +1298,7 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     if (e != hipSuccess) return e;
     const int groups = (b.max_n + 3) / 4;
     const int owned = (groups + p.split - 1) / p.split;
-    return owned <= b.threads ? launch_split_one<Real, 1>(p, P, Q, s) : launch_split_one<Real, 0>(p, P, Q, s);
+    return launch_split_one<Real>(p, P, Q, owned <= b.threads ? 1 : 0, s);
 }
 
 // All launches of one run: a split launch, one bucket on the caller's

@@ -9,6 +9,8 @@
 //     D = F_tau(v_a) + F_tau+1(v_b) - F_tau(v_b) - F_tau+1(v_a),
 // the draw U = (w >> 8) 2^-24 from word 0 of Philox4x32-10 at counter
 // (t mod 2^32, a, 2^31 - 1, t div 2^32) with the sweep generator's key.
+// In the size-clustered model every clause contributes the free energy of
+// its own group's RBM.
 #include <hip/hip_runtime.h>
 
 #include "hp_internal.hpp"
@@ -40,7 +42,30 @@ __global__ void fe_table_kernel(const double *__restrict__ W, const double *__re
     fe[i] = f;
 }
 
-// F_tau(v) of every (formula, chain) for every temperature: [F][B][T]
+// Size-clustered model: fe[tau][r] over the 248 pattern rows of the five
+// groups (group K at row 2^K - 8), each with its own RBM.
+__global__ void fe_table_clust_kernel(ClustRbm R, int T, double *__restrict__ fe) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T * kClustThrRows) return;
+    const int tau = i / kClustThrRows, row = i % kClustThrRows;
+    const int K = 31 - __clz(row + 8), L = clust_hidden(K), m = row - ((1 << K) - 8);
+    double f = 0.0;
+    if (R.W[K - 3]) {
+        const double *Wt = R.W[K - 3] + (size_t)tau * K * L;
+        for (int l = 0; l < L; ++l) {
+            double z = R.b[K - 3][tau * L + l];
+            for (int k = 0; k < K; ++k)
+                if ((m >> k) & 1) z += Wt[k * L + l];
+            f -= softplus(z);
+        }
+    }
+    fe[i] = f;
+}
+
+// F_tau(v) of every (formula, chain) for every temperature: [F][B][T].
+// kClust: a clause of length len reads row 2^K - 8 + m of the clustered
+// table, K = max(len, 3), m its pattern padded to K inputs.
+template <bool kClust>
 __global__ __launch_bounds__(kFeThreads) void free_energy_kernel(const FormulaDev *__restrict__ fd,
                                                                  const WorkItem *__restrict__ work,
                                                                  const uint4 *__restrict__ rec, int B, int T,
@@ -63,8 +88,15 @@ __global__ __launch_bounds__(kFeThreads) void free_energy_kernel(const FormulaDe
         for (uint32_t k = 0; k < len; ++k) m |= (uint32_t)(vb[e[k] & 0x7fffu] & 1u) << k;
         const uint32_t lenmask = (1u << len) - 1u;
         m = (m ^ negm) & lenmask;
-        m |= (m & 1u) ? (full & ~lenmask) : 0u;          // padding copies of literal 0
-        for (int t = 0; t < T; ++t) acc[t] += fe[t * kPatterns + m];
+        if (kClust) {
+            const uint32_t Kc = len < 3u ? 3u : len;
+            m |= (m & 1u) ? (((1u << Kc) - 1u) & ~lenmask) : 0u;
+            const uint32_t row = (1u << Kc) - 8u + m;
+            for (int t = 0; t < T; ++t) acc[t] += fe[t * kClustThrRows + row];
+        } else {
+            m |= (m & 1u) ? (full & ~lenmask) : 0u;          // padding copies of literal 0
+            for (int t = 0; t < T; ++t) acc[t] += fe[t * kPatterns + m];
+        }
     }
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (int t = 0; t < T; ++t) {
@@ -114,17 +146,25 @@ __global__ void swap_kernel(const int32_t *__restrict__ temp_old, int32_t *__res
 
 hipError_t launch_temper(Plan &p, const hp_state &st, int parity, hipStream_t s) {
     const size_t items = (size_t)p.F * p.B;
+    const int rows = p.clust ? kClustThrRows : kPatterns;
     if (!p.d_fe) {
-        hipError_t e = hipMalloc((void **)&p.d_fe, (size_t)p.T * kPatterns * sizeof(double));
+        hipError_t e = hipMalloc((void **)&p.d_fe, (size_t)p.T * rows * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void **)&p.d_fe_chain, items * p.T * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void **)&p.d_temp_old, items * sizeof(int32_t));
         if (e != hipSuccess) return e;
-        fe_table_kernel<<<(p.T * kPatterns + 255) / 256, 256, 0, s>>>(p.d_W, p.d_b, p.K, p.L, p.T, p.d_fe);
+        if (p.clust)
+            fe_table_clust_kernel<<<(p.T * rows + 255) / 256, 256, 0, s>>>(p.crbm, p.T, p.d_fe);
+        else
+            fe_table_kernel<<<(p.T * rows + 255) / 256, 256, 0, s>>>(p.d_W, p.d_b, p.K, p.L, p.T, p.d_fe);
     }
     hipError_t e = hipMemcpyAsync(p.d_temp_old, p.d_temp, items * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
-    free_energy_kernel<<<(unsigned)items, kFeThreads, 0, s>>>(p.d_fd, p.d_work_fb, p.d_rec, p.B, p.T,
-                                                              (1u << p.K) - 1u, st.v, p.d_fe, p.d_fe_chain);
+    if (p.clust)
+        free_energy_kernel<true><<<(unsigned)items, kFeThreads, 0, s>>>(p.d_fd, p.d_work_fb, p.d_rec, p.B, p.T, 0u,
+                                                                        st.v, p.d_fe, p.d_fe_chain);
+    else
+        free_energy_kernel<false><<<(unsigned)items, kFeThreads, 0, s>>>(p.d_fd, p.d_work_fb, p.d_rec, p.B, p.T,
+                                                                         (1u << p.K) - 1u, st.v, p.d_fe, p.d_fe_chain);
     swap_kernel<<<p.F, 64, 0, s>>>(p.d_temp_old, p.d_temp, p.d_fe_chain, p.B, p.T, parity, st.t,
                                    (uint32_t)(p.seed & 0xffffffffu), (uint32_t)(p.seed >> 32));
     return hipGetLastError();

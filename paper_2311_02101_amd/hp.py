@@ -46,7 +46,7 @@ class HpOpts(ct.Structure):
     _fields_ = [("chains", ct.c_int32), ("temp_of_chain", ct.POINTER(ct.c_int32)),
                 ("precision", ct.c_int32), ("alpha", ct.c_double), ("seed", ct.c_uint64),
                 ("threads", ct.c_int32), ("split", ct.c_int32), ("kernel", ct.c_int32),
-                ("graph", ct.c_int32)]
+                ("graph", ct.c_int32), ("size_rbms", ct.c_void_p)]
 
 
 class HpPlanInfo(ct.Structure):
@@ -160,11 +160,14 @@ class Plan:
     """A planned formula batch (``hp_plan``); call ``run`` with a ``State``.
 
     tables: list of per-formula signed 1-based [K][C_f] literal tables.
-    n_vars: list of N_f.  W: [T][K][L], b: [T][L] canonical OR-gate RBMs."""
+    n_vars: list of N_f.  W: [T][K][L], b: [T][L] canonical OR-gate RBMs.
+    size_rbms: None, or the size-clustered model (Sec. 4): a dict K -> (W
+    [T][K][L_K], b [T][L_K]) for K = 3 .. max(K, 3), L_K = 3 for K = 3 and
+    K + 1 otherwise; each clause then uses the RBM of its own length."""
 
     def __init__(self, tables, n_vars, W, b, *, chains, temps=None, precision="f64",
                  alpha=1e-3, seed=0, threads=0, split=0, kernel="auto", graph=False,
-                 stream=None):
+                 stream=None, size_rbms=None):
         lib = load()
         tables = [np.asarray(t, dtype=np.int32) for t in tables]
         n_vars = [int(n) for n in n_vars]
@@ -190,8 +193,22 @@ class Plan:
             if self.temps.shape != (self.B,):
                 raise ValueError("temps must have one entry per chain")
             tp = _ptr(self.temps, ct.c_int32)
+        sr = None
+        self.clustered = size_rbms is not None
+        if size_rbms is not None:
+            self._size_arrays = []
+            sr = (HpRbm * 5)()
+            for i, Kg in enumerate(range(3, max(K, 3) + 1)):
+                Wg, bg = size_rbms[Kg]
+                Lg = 3 if Kg == 3 else Kg + 1
+                Wg = np.ascontiguousarray(np.asarray(Wg, dtype=np.float64).reshape(-1, Kg, Lg))
+                bg = np.ascontiguousarray(np.asarray(bg, dtype=np.float64).reshape(Wg.shape[0], Lg))
+                self._size_arrays += [Wg, bg]
+                sr[i] = HpRbm(Kg, Lg, Wg.shape[0], _ptr(Wg, ct.c_double), _ptr(bg, ct.c_double))
+            self._size_struct = sr
         opts = HpOpts(self.B, tp, PRECISION[precision], float(alpha), int(seed) & (2 ** 64 - 1),
-                      int(threads), int(split), KERNEL[kernel], int(bool(graph)))
+                      int(threads), int(split), KERNEL[kernel], int(bool(graph)),
+                      ct.cast(sr, ct.c_void_p) if sr is not None else None)
         h = ct.c_void_p()
         _check(lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts),
                            _stream_handle(stream)))

@@ -153,6 +153,17 @@ def pretrained_rbm(k: int, targets=FSTAR_PAIR):
     return np.stack(ws), np.stack(bs), np.array(res)
 
 
+def pretrained_size_rbms(targets=FSTAR_PAIR, k_max: int = 7):
+    """The canonical RBMs of the size-clustered model (Sec. 4): {K: (W [T][K][L_K],
+    b [T][L_K])} for K = 3 .. k_max, L_K = 3 for K = 3 and K + 1 otherwise,
+    fitted to the same F* targets."""
+    out = {}
+    for K in range(3, max(k_max, 3) + 1):
+        W, b, _ = pretrained_rbm(K, targets)
+        out[K] = (W, b)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # DIMACS CNF reader (unweighted, "p cnf N C" header, 0-terminated clauses)
 # ---------------------------------------------------------------------------
@@ -222,6 +233,7 @@ class Workload:
     b: np.ndarray = None    # [T][L]
     temps: np.ndarray = None  # [B]
     alpha: float = 1e-3
+    size_rbms: dict = None    # size-clustered model {K: (W, b)}, None = padded
 
 
 def make_workload(name: str, n_vars, chains: int, seed: int, *, sweeps: int = 500,

@@ -55,8 +55,18 @@ def _plan_status(lib, tables, ns, W, b, **kw):
                    hp._ptr(W, ct.c_double), hp._ptr(b, ct.c_double))
     temps = kw.get("temps")
     tp = hp._ptr(np.asarray(temps, np.int32), ct.c_int32) if temps is not None else None
+    sr = None
+    if "size" in kw:                 # size-clustered model: [(k, l, n_temps, scale)] for K = 3..
+        keep = []
+        sr = (hp.HpRbm * 5)()
+        for i, (k, l, t, scale) in enumerate(kw["size"]):
+            Wg = np.full((max(t, 1), k, max(l, 1)), scale)
+            bg = np.zeros((max(t, 1), max(l, 1)))
+            keep += [Wg, bg]
+            sr[i] = hp.HpRbm(k, l, t, hp._ptr(Wg, ct.c_double), hp._ptr(bg, ct.c_double))
     opts = hp.HpOpts(kw.get("B", 2), tp, kw.get("prec", hp.HP_FP64), kw.get("alpha", 1e-3), 0,
-                     kw.get("threads", 0), kw.get("split", 0), kw.get("kernel", 0))
+                     kw.get("threads", 0), kw.get("split", 0), kw.get("kernel", 0), 0,
+                     ct.cast(sr, ct.c_void_p) if sr is not None else None)
     h = ct.c_void_p()
     st = lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts), None)
     assert not h.value            # never a partial plan
@@ -82,6 +92,14 @@ CASES = [
     ("split not a power of two", dict(split=3), hp.HP_EINVAL),
     ("split too large", dict(split=32), hp.HP_EINVAL),
     ("unknown kernel variant", dict(kernel=5), hp.HP_EINVAL),
+    ("size RBM with the wrong L", dict(size=[(3, 4, 2, 0.1)]), hp.HP_EINVAL),
+    ("size RBM with the wrong K", dict(size=[(4, 5, 2, 0.1)]), hp.HP_EINVAL),
+    ("size RBM with another n_temps", dict(size=[(3, 3, 1, 0.1)]), hp.HP_EINVAL),
+    ("size RBM with a NaN weight", dict(size=[(3, 3, 2, float("nan"))]), hp.HP_EINVAL),
+    ("size-clustered model in mixed precision", dict(size=[(3, 3, 2, 0.1)], prec=hp.HP_MIXED_BF16),
+     hp.HP_EUNSUPPORTED),
+    ("size-clustered model with the pull kernel", dict(size=[(3, 3, 2, 0.1)], kernel=hp.KERNEL["pull"]),
+     hp.HP_EUNSUPPORTED),
 ]
 
 
