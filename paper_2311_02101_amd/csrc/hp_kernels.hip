@@ -882,13 +882,18 @@ struct SplitCtx {
 // 4): it keeps its own partial logits of those in LDS, publishes the others,
 // sums the G partials of its own variables exactly (integers), draws their new
 // values and publishes them; then every member reads the new values of the
-// groups it does not own.
+// groups it does not own.  The owner's visible phase runs one variable per
+// thread (variable own_lo + tid + j NT, j < VPT): the four threads of a group
+// evaluate the group's Philox block alike and each takes its own word, and
+// the group's first thread packs the four new values into the published word.
 template <typename Real, int VPT, bool kClust>
 __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const SplitParams &Q, const SplitCtx<Real> &c,
-                                             Real (&nu)[VPT > 0 ? VPT : 1][4], int &smax, uint32_t &phase) {
+                                             Real (&nu)[VPT > 0 ? VPT : 1], const int32_t (&ncr)[VPT > 0 ? VPT : 1],
+                                             int &smax, uint32_t &phase) {
     const PushLds &L = c.L;
     const int G = c.G, g = c.g, N = c.N, tid = c.tid, NT = c.NT;
     const int own_lo = c.q_lo * 4, own_hi = min(N, c.q_hi * 4);
+    const int jmax = VPT > 0 ? VPT : (own_hi - own_lo + NT - 1) / NT;
     for (int64_t s = 0; s < c.S; ++s) {
         const uint64_t t = (uint64_t)(c.t0 + s);
         const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
@@ -913,71 +918,49 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         for (int k = 0; k < G; ++k) total += xload(&c.pcnt[k]);
         const bool improved = total > smax;
         if (improved) smax = total;
-        // visible phase on the owned groups
+        // visible phase on the owned variables
 #pragma unroll
         for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
-            const int jmax = VPT > 0 ? j + 1 : (c.q_hi - c.q_lo + NT - 1) / NT;
-            for (int jj = (VPT > 0 ? j : 0); jj < jmax; ++jj) {
-                const int grp = c.q_lo + tid + jj * NT;
-                if (grp < c.q_hi) {
-                    uint4 r = make_uint4(0, 0, 0, 0);
-                    if (c.sample)
-                        r = philox4x32_10(make_uint4(tlo, (uint32_t)c.b, kPhaseVisible | (uint32_t)grp, thi), c.key);
-                    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-                    // sum the partial logits of the group's 4 variables: all
-                    // loads of a batch of members are issued before any is
-                    // used, so the group pays one memory round trip per
-                    // batch instead of one per variable
-                    int64_t xs[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int i = grp * 4 + q;
-                        xs[q] = 0;
-                        if (c.sample && i < N) {
-                            xs[q] = (int64_t)c.negcnt[i] + L.x[i];
-                            L.x[i] = 0;
-                        }
-                    }
+            for (int jj = (VPT > 0 ? j : 0); jj < (VPT > 0 ? j + 1 : jmax); ++jj) {
+                const int i = own_lo + tid + jj * NT;
+                const bool act = i < own_hi;
+                uint32_t nvb = 0;
+                if (act) {
+                    if (improved) P.best[c.sbase + i] = L.v[i];
                     if (c.sample) {
+                        const uint4 r =
+                            philox4x32_10(make_uint4(tlo, (uint32_t)c.b, kPhaseVisible | (uint32_t)(i >> 2), thi), c.key);
+                        const int q = i & 3;
+                        const uint32_t word = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+                        // the partials of the other members: a batch of loads
+                        // in flight before any is used
+                        int64_t xs = (int64_t)(VPT > 0 ? ncr[j] : c.negcnt[i]) + L.x[i];
+                        L.x[i] = 0;
                         for (int k0 = 0; k0 < G; k0 += 4) {
-                            int64_t part[4][4];
+                            int64_t pk[4];
 #pragma unroll
-                            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    const int k = k0 + kk, i = grp * 4 + q;
-                                    part[kk][q] = (k < G && k != g && i < N)
-                                                      ? xload(&c.xpart[(size_t)k * c.nstride + i])
-                                                      : 0;
-                                }
-#pragma unroll
-                            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) xs[q] += part[kk][q];
-                        }
-                    }
-                    uint32_t packed = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int i = grp * 4 + q;
-                        if (i < N) {
-                            if (improved) P.best[c.sbase + i] = L.v[i];
-                            if (c.sample) {
-                                const int64_t xi = xs[q];
-                                uint8_t nvb;
-                                if (VPT > 0) {
-                                    nvb = visible_update(xi, c.fx_scale, nu[j][q], c.alpha, rw[q]);
-                                } else {
-                                    Real nv = P.nu[c.sbase + i];
-                                    nvb = visible_update(xi, c.fx_scale, nv, c.alpha, rw[q]);
-                                    P.nu[c.sbase + i] = nv;
-                                }
-                                L.v[i] = nvb;
-                                packed |= (uint32_t)nvb << (8 * q);
+                            for (int kk = 0; kk < 4; ++kk) {
+                                const int k = k0 + kk;
+                                pk[kk] = (k < G && k != g) ? xload(&c.xpart[(size_t)k * c.nstride + i]) : 0;
                             }
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk) xs += pk[kk];
                         }
+                        if (VPT > 0) {
+                            nvb = visible_update(xs, c.fx_scale, nu[j], c.alpha, word);
+                        } else {
+                            Real nv = P.nu[c.sbase + i];
+                            nvb = visible_update(xs, c.fx_scale, nv, c.alpha, word);
+                            P.nu[c.sbase + i] = nv;
+                        }
+                        L.v[i] = (uint8_t)nvb;
                     }
-                    if (c.sample) xstore(&c.vbuf[grp], packed);
+                }
+                if (c.sample) {
+                    // own_lo and NT are multiples of 4: thread tid holds word i & 3 = tid & 3
+                    const uint32_t b1 = __shfl_down(nvb, 1, kWave), b2 = __shfl_down(nvb, 2, kWave),
+                                   b3 = __shfl_down(nvb, 3, kWave);
+                    if (act && (tid & 3) == 0) xstore(&c.vbuf[i >> 2], nvb | (b1 << 8) | (b2 << 16) | (b3 << 24));
                 }
             }
         }
@@ -1057,35 +1040,31 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
         L.v[i] = P.v[c.sbase + i];
         L.x[i] = 0;
     }
+    // EMA and negation count of the owned variables own_lo + tid + j NT
     constexpr int VR = VPT > 0 ? VPT : 1;
-    Real nu[VR][4];
-    if (VPT > 0) {
+    const int own_lo = c.q_lo * 4, own_hi = min(N, c.q_hi * 4);
+    Real nu[VR];
+    int32_t ncr[VR];
 #pragma unroll
-        for (int j = 0; j < VR; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int grp = c.q_lo + tid + j * NT;
-                const int i = grp * 4 + q;
-                nu[j][q] = (grp < c.q_hi && i < N) ? P.nu[c.sbase + i] : Real(0);
-            }
+    for (int j = 0; j < VR; ++j) {
+        const int i = own_lo + tid + j * NT;
+        nu[j] = (VPT > 0 && i < own_hi) ? P.nu[c.sbase + i] : Real(0);
+        ncr[j] = (VPT > 0 && i < own_hi) ? c.negcnt[i] : 0;
     }
     int smax = P.s_max[(int64_t)w.f * P.B + w.b];
     c.t0 = *P.t_ptr;
     __syncthreads();
 
-    split_sweeps<Real, VPT, kClust>(P, Q, c, nu, smax, phase);
+    split_sweeps<Real, VPT, kClust>(P, Q, c, nu, ncr, smax, phase);
 
     // write back the owned part of the state
-    for (int i = c.q_lo * 4 + tid; i < min(N, c.q_hi * 4); i += NT) P.v[c.sbase + i] = L.v[i];
+    for (int i = own_lo + tid; i < own_hi; i += NT) P.v[c.sbase + i] = L.v[i];
     if (VPT > 0) {
 #pragma unroll
-        for (int j = 0; j < VR; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int grp = c.q_lo + tid + j * NT;
-                const int i = grp * 4 + q;
-                if (grp < c.q_hi && i < N) P.nu[c.sbase + i] = nu[j][q];
-            }
+        for (int j = 0; j < VR; ++j) {
+            const int i = own_lo + tid + j * NT;
+            if (i < own_hi) P.nu[c.sbase + i] = nu[j];
+        }
     }
     if (g == 0 && tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;
 }
@@ -1124,11 +1103,16 @@ const void *clust_kernel_ptr(int vpt) {
     }
 }
 
+// owned variables per thread of a split member: 1 or 2 in registers, else 0
 template <typename Real>
 const void *split_kernel_ptr(bool clust, int vpt) {
     if (clust)
-        return vpt == 1 ? (const void *)sweep_split_kernel<Real, 1, true> : (const void *)sweep_split_kernel<Real, 0, true>;
-    return vpt == 1 ? (const void *)sweep_split_kernel<Real, 1> : (const void *)sweep_split_kernel<Real, 0>;
+        return vpt == 1 ? (const void *)sweep_split_kernel<Real, 1, true>
+               : vpt == 2 ? (const void *)sweep_split_kernel<Real, 2, true>
+                          : (const void *)sweep_split_kernel<Real, 0, true>;
+    return vpt == 1 ? (const void *)sweep_split_kernel<Real, 1>
+           : vpt == 2 ? (const void *)sweep_split_kernel<Real, 2>
+                      : (const void *)sweep_split_kernel<Real, 0>;
 }
 
 const void *mixed_kernel_ptr(int vpt) {
@@ -1154,8 +1138,9 @@ hipError_t set_limits_t(int bytes) {
                         push_kernel_ptr<Real>(1, true),  push_kernel_ptr<Real>(2, true),  push_kernel_ptr<Real>(0, true),
                         pull_kernel_ptr<Real>(1),        pull_kernel_ptr<Real>(2),        pull_kernel_ptr<Real>(0),
                         clust_kernel_ptr<Real>(1),       clust_kernel_ptr<Real>(2),       clust_kernel_ptr<Real>(0),
-                        split_kernel_ptr<Real>(false, 1), split_kernel_ptr<Real>(false, 0),
-                        split_kernel_ptr<Real>(true, 1),  split_kernel_ptr<Real>(true, 0)};
+                        split_kernel_ptr<Real>(false, 1), split_kernel_ptr<Real>(false, 2),
+                        split_kernel_ptr<Real>(false, 0), split_kernel_ptr<Real>(true, 1),
+                        split_kernel_ptr<Real>(true, 2),  split_kernel_ptr<Real>(true, 0)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -1297,8 +1282,8 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     hipError_t e = launch_zero(p.d_bar, (int64_t)b.count * 32, s);
     if (e != hipSuccess) return e;
     const int groups = (b.max_n + 3) / 4;
-    const int owned = (groups + p.split - 1) / p.split;
-    return launch_split_one<Real>(p, P, Q, owned <= b.threads ? 1 : 0, s);
+    const int owned = 4 * ((groups + p.split - 1) / p.split);   // variables per member
+    return launch_split_one<Real>(p, P, Q, owned <= b.threads ? 1 : owned <= 2 * b.threads ? 2 : 0, s);
 }
 
 // All launches of one run: a split launch, one bucket on the caller's

@@ -143,22 +143,27 @@ def main(argv=None):
     ap.add_argument("--targets", type=int, default=2, choices=[2, 16],
                     help="free-energy targets: the pair of the 1-accelerator runs or the 16-target list")
     ap.add_argument("--formulas", type=int, default=0, help="limit a batch workload to its first formulas")
+    ap.add_argument("--model", default="padded", choices=["padded", "clustered"],
+                    help="padded formula-RBM or the size-clustered one (an RBM per clause length)")
     args = ap.parse_args(argv)
     w = wl.config_workload(args.workload, precision=args.precision)
     tables, n_vars, v0 = w.tables, w.n_vars, w.v0
     W, b, temps = w.W, w.b, w.temps
+    targets = wl.FSTAR_PAIR
     if args.targets == 16:
+        targets = wl.FSTAR_16
         W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_16)
         temps = wl.default_temperatures(w.chains, 16)
+    size_rbms = wl.pretrained_size_rbms(targets) if args.model == "clustered" else None
     if args.formulas:
         tables, n_vars, v0 = tables[:args.formulas], n_vars[:args.formulas], v0[:args.formulas]
     out = {"workload": args.workload, "sweeps": args.sweeps, "upp": args.upp, "upw": args.upw,
            "temper_every": args.temper, "targets": args.targets, "chains": w.chains, "formulas": len(tables),
-           "host_threads": args.threads}
+           "host_threads": args.threads, "model": args.model}
 
     def run(sweeps, upp=0, temper=0):
         plan = hp.Plan(tables, n_vars, W, b, chains=w.chains, temps=temps, precision=args.precision,
-                       alpha=w.alpha, seed=w.seed)
+                       alpha=w.alpha, seed=w.seed, size_rbms=size_rbms)
         st = plan.new_state(v0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -316,6 +316,19 @@ def test_split_fp32_and_global_ema_path(hip):
     _same(ref, got)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_split_two_owned_variables_per_thread(hip, prec):
+    """512 threads per member owning 1024 variables (EMA of two variables per
+    thread in registers), N not a multiple of 4."""
+    n = 4094
+    T = wl.random_formula(n, 32)
+    W, b = wl.gaussian_rbm(2, 7, 8, 32)
+    say(f"[split {prec}, 512 threads] N={n} 8 chains, split 4")
+    ref, _ = _run_states([T], [n], W, b, 8, 15, prec, 32, split=1, threads=512)
+    got, _ = _run_states([T], [n], W, b, 8, 15, prec, 32, split=4, threads=512)
+    _same(ref, got)
+
+
 def test_split_tiny_ragged_members(hip):
     """Members that own no variables or no clauses."""
     clauses = [[[5, -1, 2], [-3, 4], [1], [-5, 2, 3]], [[1, -2], [2]]]
