@@ -537,6 +537,25 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         else bk.grid = 0;                 // split launches run one item per group
     }
     p->split = G;
+    if (G > 1) {
+        // member-major record order: member g of a split chain takes every
+        // G-th record of the length-sorted order (the same length mix for
+        // every member), stored contiguously so its loads are unit-stride;
+        // member g's run starts at g floor(C/G) + min(g, C mod G)
+        std::vector<uint4> r2(NC);
+        std::vector<uint32_t> o2(NC);
+        for (int f = 0; f < F; ++f) {
+            const int64_t c0 = cnf->clause_offset[f], C = cnf->clause_offset[f + 1] - c0;
+            const int64_t q = C / G, rem = C % G;
+            for (int64_t j = 0; j < C; ++j) {
+                const int64_t g = j % G, pos = g * q + std::min<int64_t>(g, rem) + j / G;
+                r2[c0 + pos] = rec[c0 + j];
+                o2[c0 + pos] = orig[c0 + j];
+            }
+        }
+        rec.swap(r2);
+        orig.swap(o2);
+    }
     p->nstride = ((int64_t)p->buckets[0].max_n + 127) / 128 * 128;   // 128-byte lines per item
     p->xcd_map = (p->buckets[0].count % 8 == 0) ? 1 : 0;
     p->use_graph = opts->graph ? 1 : 0;

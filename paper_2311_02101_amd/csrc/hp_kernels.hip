@@ -874,6 +874,7 @@ struct SplitCtx {
     double fx_scale;
     Real alpha;
     int G, g, N, C, tid, NT, b, groups, q_lo, q_hi;
+    int c_lo, c_hi;              // this member's run of records
     uint32_t nbh, full, lmask;
     bool sample;
 };
@@ -897,12 +898,12 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
     for (int64_t s = 0; s < c.S; ++s) {
         const uint64_t t = (uint64_t)(c.t0 + s);
         const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-        // member g takes every G-th record of the length-sorted order, so all
-        // members get the same mix of clause lengths
-        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi,
+        // member g's records: every G-th of the length-sorted order (the same
+        // mix of clause lengths for all members), stored as one contiguous run
+        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, tlo, thi,
                                                               (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask)
-                                 : clause_phase<false, kClust>(L, c.rec, c.orig, g, G, c.C, tid, NT, tlo, thi,
-                                                               (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask);
+                                 : clause_phase<false, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, tlo,
+                                                               thi, (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask);
         const int part = block_total(L, cnt, tid, NT);
         // publish the partial logits of the variables other members own
         if (c.sample) {
@@ -1007,6 +1008,8 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.g = g;
     c.N = N;
     c.C = fd.c;
+    c.c_lo = g * (fd.c / G) + min(g, fd.c % G);
+    c.c_hi = c.c_lo + fd.c / G + (g < fd.c % G ? 1 : 0);
     c.tid = tid;
     c.NT = NT;
     c.b = w.b;
