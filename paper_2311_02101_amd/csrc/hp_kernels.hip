@@ -441,11 +441,58 @@ __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_
     }
 }
 
+// Gather of a clause's literal values: bit k of the result is the value of
+// the variable of slot k (polarity not applied), for slots 0..len-1.
+template <int LEN>
+__device__ __forceinline__ uint32_t gather_fixed(const uint8_t *v, const uint4 &r) {
+    const uint32_t e[7] = {r.x, r.x >> 16, r.y, r.y >> 16, r.z, r.z >> 16, r.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) m |= (uint32_t)v[e[k] & 0x7fffu] << k;
+    return m;
+}
+
+__device__ __forceinline__ uint32_t gather_any(const uint8_t *v, const uint4 &r, uint32_t len) {
+    uint32_t m = v[r.x & 0x7fffu];
+    if (len > 1) m |= (uint32_t)v[(r.x >> 16) & 0x7fffu] << 1;
+    if (len > 2) m |= (uint32_t)v[r.y & 0x7fffu] << 2;
+    if (len > 3) m |= (uint32_t)v[(r.y >> 16) & 0x7fffu] << 3;
+    if (len > 4) m |= (uint32_t)v[r.z & 0x7fffu] << 4;
+    if (len > 5) m |= (uint32_t)v[(r.z >> 16) & 0x7fffu] << 5;
+    if (len > 6) m |= (uint32_t)v[r.w & 0x7fffu] << 6;
+    return m;
+}
+
+// Scatter of a clause's contributions: g0 (the merged slot 0) to slot 0's
+// variable, gr[k] to slot k's for k = 1..len-1.
+template <int LEN>
+__device__ __forceinline__ void scatter_fixed(int64_t *x, const uint4 &r, int64_t g0, const int64_t *gr) {
+    const uint32_t e[7] = {r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16, r.z & 0xffffu, r.z >> 16,
+                           r.w & 0xffffu};
+    push_add(x, e[0], g0);
+#pragma unroll
+    for (int k = 1; k < LEN; ++k) push_add(x, e[k], gr[k]);
+}
+
+__device__ __forceinline__ void scatter_any(int64_t *x, const uint4 &r, uint32_t len, int64_t g0,
+                                            const int64_t *gr) {
+    push_add(x, r.x & 0xffffu, g0);
+    if (len > 1) push_add(x, r.x >> 16, gr[1]);
+    if (len > 2) push_add(x, r.y & 0xffffu, gr[2]);
+    if (len > 3) push_add(x, r.y >> 16, gr[3]);
+    if (len > 4) push_add(x, r.z & 0xffffu, gr[4]);
+    if (len > 5) push_add(x, r.z >> 16, gr[5]);
+    if (len > 6) push_add(x, r.w & 0xffffu, gr[6]);
+}
+
 // Clause phase over the clause records c = c_first + c_step * j, c < c_end,
 // j strided over the workgroup:
 // gather, literal-truth pattern, count; when sampling, the hidden draw and the
 // scatter of the clause's contributions into the LDS accumulators.  Returns
-// this thread's number of satisfied clauses.
+// this thread's number of satisfied clauses.  Records are sorted by length,
+// so the 64 lanes of a wave nearly always hold clauses of one length: then
+// the gather and scatter run unrolled for that length under a scalar branch
+// (ul > 0), else per-lane length tests (ul = 0).
 //
 // kClust: the size-clustered model; a clause of length len takes the tables
 // of group K = max(len, 3) (L = 3 or K + 1 hidden units, drawn from blocks
@@ -472,16 +519,20 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
         }
         const uint32_t len = (r.w >> 16) & 7u;
         const uint32_t negm = r.w >> 19;          // negation bits of slots 0..len-1
-        const uint32_t e0 = r.x & 0xffffu, e1 = r.x >> 16, e2 = r.y & 0xffffu, e3 = r.y >> 16;
-        const uint32_t e4 = r.z & 0xffffu, e5 = r.z >> 16, e6 = r.w & 0xffffu;
+        const int lu = __builtin_amdgcn_readfirstlane((int)len);
+        const int ul = __all((int)len == lu) ? lu : 0;
         // gather the values of the clause's variables, then apply the polarities
-        uint32_t m = L.v[e0 & 0x7fffu];
-        if (len > 1) m |= (uint32_t)L.v[e1 & 0x7fffu] << 1;
-        if (len > 2) m |= (uint32_t)L.v[e2 & 0x7fffu] << 2;
-        if (len > 3) m |= (uint32_t)L.v[e3 & 0x7fffu] << 3;
-        if (len > 4) m |= (uint32_t)L.v[e4 & 0x7fffu] << 4;
-        if (len > 5) m |= (uint32_t)L.v[e5 & 0x7fffu] << 5;
-        if (len > 6) m |= (uint32_t)L.v[e6 & 0x7fffu] << 6;
+        uint32_t m;
+        switch (ul) {
+            case 1: m = gather_fixed<1>(L.v, r); break;
+            case 2: m = gather_fixed<2>(L.v, r); break;
+            case 3: m = gather_fixed<3>(L.v, r); break;
+            case 4: m = gather_fixed<4>(L.v, r); break;
+            case 5: m = gather_fixed<5>(L.v, r); break;
+            case 6: m = gather_fixed<6>(L.v, r); break;
+            case 7: m = gather_fixed<7>(L.v, r); break;
+            default: m = gather_any(L.v, r, len);
+        }
         m ^= negm;
         if (kClust) {
             const uint32_t Kc = len < 3u ? 3u : len;
@@ -492,6 +543,7 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
         cnt += (m != 0u);
         if (kSample) {
             uint32_t n;
+            int64_t g0;
             const int64_t *gr;
             if (kClust) {
                 const uint32_t Kc = len < 3u ? 3u : len;
@@ -499,19 +551,23 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
                 n = hidden_mask(L.thr + ((1u << Kc) - 8u + m) * kMaxL, tlo, thi, chain, oc * 2u, key,
                                 big ? 2u : 1u) &
                     (big ? (2u << Kc) - 1u : 7u);
-                push_add(L.x, e0, L.gpad[(len <= 3u ? 8u * (len - 1u) : (2u << len) - 8u) + n]);
+                g0 = L.gpad[(len <= 3u ? 8u * (len - 1u) : (2u << len) - 8u) + n];
                 gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
             } else {
                 n = hidden_mask(L.thr + m * kMaxL, tlo, thi, chain, oc * nbh, key, nbh) & lmask;
-                push_add(L.x, e0, L.gpad[len * kHidMasks + n]);
+                g0 = L.gpad[len * kHidMasks + n];
                 gr = L.gfx + n * kMaxL;
             }
-            if (len > 1) push_add(L.x, e1, gr[1]);
-            if (len > 2) push_add(L.x, e2, gr[2]);
-            if (len > 3) push_add(L.x, e3, gr[3]);
-            if (len > 4) push_add(L.x, e4, gr[4]);
-            if (len > 5) push_add(L.x, e5, gr[5]);
-            if (len > 6) push_add(L.x, e6, gr[6]);
+            switch (ul) {
+                case 1: scatter_fixed<1>(L.x, r, g0, gr); break;
+                case 2: scatter_fixed<2>(L.x, r, g0, gr); break;
+                case 3: scatter_fixed<3>(L.x, r, g0, gr); break;
+                case 4: scatter_fixed<4>(L.x, r, g0, gr); break;
+                case 5: scatter_fixed<5>(L.x, r, g0, gr); break;
+                case 6: scatter_fixed<6>(L.x, r, g0, gr); break;
+                case 7: scatter_fixed<7>(L.x, r, g0, gr); break;
+                default: scatter_any(L.x, r, len, g0, gr);
+            }
         }
     }
     return cnt;
