@@ -229,24 +229,25 @@ size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off) {
 // set iff word_l <= row[l] (i.e. U < p_l).  Units of the first Philox block
 // go to bits 0..3, of the second block (L > 4) to bits 4..7; bits >= L are
 // left to the caller to mask.
+__device__ __forceinline__ uint32_t draw4(const uint4 &r, const uint4 &t) {
+    uint32_t n = (uint32_t)(r.w <= t.w);
+    n = n + n + (uint32_t)(r.z <= t.z);
+    n = n + n + (uint32_t)(r.y <= t.y);
+    return n + n + (uint32_t)(r.x <= t.x);
+}
+
 __device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t tlo, uint32_t thi,
                                                 uint32_t chain, uint32_t blk, Key2 key, uint32_t nbh) {
     const uint4 ta = *reinterpret_cast<const uint4 *>(row);
-    const uint4 ra = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | blk, thi), key);
-    uint32_t n = (uint32_t)(ra.w <= ta.w);
-    n = n + n + (uint32_t)(ra.z <= ta.z);
-    n = n + n + (uint32_t)(ra.y <= ta.y);
-    n = n + n + (uint32_t)(ra.x <= ta.x);
+    uint4 ra = make_uint4(tlo, chain, kPhaseHidden | blk, thi);
     if (nbh > 1) {
+        // both blocks in one pass (interleaved rounds, one key schedule)
         const uint4 tb = *reinterpret_cast<const uint4 *>(row + 4);
-        const uint4 rb = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | (blk + 1u), thi), key);
-        uint32_t h = (uint32_t)(rb.w <= tb.w);
-        h = h + h + (uint32_t)(rb.z <= tb.z);
-        h = h + h + (uint32_t)(rb.y <= tb.y);
-        h = h + h + (uint32_t)(rb.x <= tb.x);
-        n |= h << 4;
+        uint4 rb = make_uint4(tlo, chain, kPhaseHidden | (blk + 1u), thi);
+        philox4x32_10_pair(ra, rb, key);
+        return draw4(ra, ta) | (draw4(rb, tb) << 4);
     }
-    return n;
+    return draw4(philox4x32_10(ra, key), ta);
 }
 
 // VPT > 0: each thread owns VPT groups of 4 consecutive variables and keeps
