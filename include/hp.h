@@ -98,11 +98,13 @@ typedef struct {
     int32_t split;                  /* workgroups per chain of the push kernel: 0 =
                                        automatic (fill the device), 1 = one, or a power
                                        of two up to 16.  The plan admits a split only
-                                       if all its workgroups fit on the device at once;
-                                       they exchange data every sweep, so a split run
-                                       must not share the device with work that keeps
-                                       CUs occupied for long (its bounded barrier waits
-                                       would time out: see hp_check)                 */
+                                       if all its workgroups fit on the device at once
+                                       and every formula has more than 4 (split - 1)
+                                       variables (HP_EUNSUPPORTED otherwise); they
+                                       exchange data every sweep, so a split run must
+                                       not share the device with work that keeps CUs
+                                       occupied for long (its bounded waits for the
+                                       other workgroups would time out: hp_check)    */
     int32_t kernel;                 /* hp_kernel: sweep kernel variant                 */
     int32_t graph;                  /* 1: hp_run replays a captured hipGraph of its
                                        launches (cached per state buffers and sweep
@@ -197,9 +199,9 @@ typedef struct {
 hp_status hp_plan_query(hp_plan_t plan, hp_plan_info *out);
 
 /* Wait for the plan's device work and report device-side failures: returns
- * HP_EDEVICE if a cross-workgroup barrier of a split launch (several
- * workgroups per chain, hp_opts.split) gave up waiting, in which case the
- * state written by the affected runs is void; HP_OK otherwise. */
+ * HP_EDEVICE if a workgroup of a split launch (several workgroups per chain,
+ * hp_opts.split) gave up waiting for the data of the others, in which case
+ * the state written by the affected runs is void; HP_OK otherwise. */
 hp_status hp_check(hp_plan_t plan);
 
 /* Release a plan's device memory (synchronises the device first).  NULL is

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -72,7 +73,6 @@ void release(Plan *p) {
     (void)hipFree(p->d_xpart);
     (void)hipFree(p->d_vbuf);
     (void)hipFree(p->d_cnt);
-    (void)hipFree(p->d_bar);
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_temp);
     (void)hipFree(p->d_fe);
@@ -363,7 +363,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     }
     // fixed-point scale: every slot contributes at most Wsum = sum |W_c| in
     // magnitude, a variable has at most max_slots slots, so |x| * 2^S stays
-    // below 2^62 when (bound + 1) * 2^S < 2^62
+    // below 2^61 when (bound + 1) * 2^S < 2^61 (the split exchange tags bits
+    // 61 and 62 of a partial sum, which needs bits 61..63 to be sign copies)
     double wsum = 0.0;
     for (int t = 0; t < T; ++t) {
         if (clust) {
@@ -383,7 +384,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     for (int64_t i = 0; i < NV; ++i) max_slots = std::max(max_slots, push_slots[i]);
     const double bound = wsum * (double)max_slots * (1.0 + 1e-9) + 8.0;
     int fx_shift = 52;
-    while (fx_shift > 0 && std::ldexp(bound + 1.0, fx_shift) >= std::ldexp(1.0, 62)) --fx_shift;
+    while (fx_shift > 0 && std::ldexp(bound + 1.0, fx_shift) >= std::ldexp(1.0, 61)) --fx_shift;
 
     // --- formula descriptors ---
     std::vector<FormulaDev> fd(F);
@@ -518,8 +519,16 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         const int occ = split_occupancy(*p);
         const int64_t capacity = (int64_t)p->cus * occ;
         const int n_items = bk.count;
+        // every member owns at least one group of 4 variables
+        int min_groups = INT32_MAX;
+        for (int f = 0; f < F; ++f) min_groups = std::min(min_groups, (fd[f].n + 3) / 4);
         if (opts->split >= 2) {
             G = opts->split;
+            if (G > min_groups) {
+                release(p);
+                return fail(HP_EUNSUPPORTED, "split " + std::to_string(G) + " needs more than " +
+                                                 std::to_string(4 * (G - 1)) + " variables in every formula");
+            }
             if ((int64_t)n_items * G > capacity) {
                 release(p);
                 return fail(HP_EUNSUPPORTED, "split " + std::to_string(G) + ": " +
@@ -530,7 +539,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         } else {
             // largest power of two that keeps every workgroup resident and
             // leaves each member at least 1024 clauses
-            while (G * 2 <= kMaxSplit && (int64_t)n_items * G * 2 <= capacity && bk.max_c / (G * 2) >= 1024)
+            while (G * 2 <= kMaxSplit && G * 2 <= min_groups && (int64_t)n_items * G * 2 <= capacity &&
+                   bk.max_c / (G * 2) >= 1024)
                 G *= 2;
         }
         if (G == 1) bk.threads = saved;   // no split: keep the bucket's own shape
@@ -645,7 +655,6 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         HP_TRY(hipMalloc((void **)&p->d_xpart, items * p->split * p->nstride * sizeof(int64_t)), "alloc xpart");
         HP_TRY(hipMalloc((void **)&p->d_vbuf, items * p->nstride), "alloc vbuf");
         HP_TRY(hipMalloc((void **)&p->d_cnt, items * kMaxSplit * sizeof(int32_t)), "alloc counts");
-        HP_TRY(hipMalloc((void **)&p->d_bar, items * 32 * sizeof(uint32_t)), "alloc barriers");
     }
     HP_TRY(launch_tables(*p, s), "table kernel");
     // host staging vectors go out of scope below: wait for the copies
@@ -795,7 +804,7 @@ hp_status hp_check(hp_plan_t plan) {
     if (e == hipSuccess) e = hipMemcpy(&flag, p->d_err, sizeof(flag), hipMemcpyDeviceToHost);
     (void)hipSetDevice(cur);
     if (e != hipSuccess) return hip_fail(e, "hp_check");
-    if (flag) return fail(HP_EDEVICE, "a cross-workgroup barrier timed out; results of the affected runs are void");
+    if (flag) return fail(HP_EDEVICE, "a split workgroup timed out waiting for the others; results of the affected runs are void");
     return HP_OK;
 }
 

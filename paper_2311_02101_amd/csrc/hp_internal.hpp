@@ -140,8 +140,7 @@ struct SplitParams {
     int64_t *xpart;              // [items][G][nstride]
     uint8_t *vbuf;               // [items][nstride]
     int32_t *cnt;                // [items][kMaxSplit] partial clause counts (64 bytes)
-    uint32_t *bar;               // [items][32] barrier counters (one 128-byte line each)
-    int32_t *err;                // [1] barrier timeout flag
+    int32_t *err;                // [1] exchange time-out flag
     int64_t nstride;
     int32_t G;
     int32_t xcd_map;             // members of an item on the same XCD
@@ -225,7 +224,6 @@ struct Plan {
     int64_t *d_xpart = nullptr;
     uint8_t *d_vbuf = nullptr;
     int32_t *d_cnt = nullptr;
-    uint32_t *d_bar = nullptr;
     int32_t *d_err = nullptr;
 };
 

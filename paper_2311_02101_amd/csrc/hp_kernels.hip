@@ -855,14 +855,12 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
 // --------------------------------------------------------------------------
 // Split kernel: G co-resident workgroups per chain
 // --------------------------------------------------------------------------
-constexpr uint32_t kSpinLimit = 1u << 25;   // ~1 s of s_sleep before giving up
-
 // Exchange between the G workgroups of one chain.  Partial logits, partial
 // counts and new values cross workgroups through global memory with relaxed
 // agent-scope atomic stores and loads: the stores write through and the loads
 // miss the CU's vector cache and the per-XCD L2, so no cache-wide write-back
 // or invalidation is needed (an agent-scope fence pair costs several
-// microseconds per barrier on MI355X).  Workgroup-scope accesses served by a
+// microseconds on MI355X).  Workgroup-scope accesses served by a
 // shared L2 are not an option for members on different CUs: outside
 // thread-group-split mode the CU's vector cache may return a stale line, and
 // the only invalidation that reaches it (buffer_inv sc1) also drops the L2's
@@ -886,36 +884,7 @@ __device__ __forceinline__ int32_t xload(const int32_t *p) {
     return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier among the G workgroups of one chain.  Counter `ctr` is zeroed
-// before the launch and incremented once per workgroup per barrier, so the
-// k-th barrier completes when it reaches k*G.  Every thread first waits until
-// its own exchange stores are acknowledged, so they are complete before the
-// workgroup's arrival is counted; the exchange loads that follow the barrier
-// are issued only after the completed count has been observed.  The wait is
-// bounded: on timeout the error flag is raised and the workgroup continues
-// (its results are then void); once the flag is up no barrier of the launch
-// waits any more, so a launch whose barriers cannot complete ends after one
-// time-out instead of one per barrier.
-__device__ __forceinline__ void group_barrier(uint32_t *ctr, uint32_t target, int32_t *err) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            if ((spins & 1023u) == 0u && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-        }
-    }
-    __syncthreads();
-}
-
-// State of one member of a split chain, shared by the two exchange variants.
+// State of one member of a split chain.
 template <typename Real>
 struct SplitCtx {
     PushLds L;
@@ -925,7 +894,6 @@ struct SplitCtx {
     int64_t *xpart;
     uint32_t *vbuf;
     int32_t *pcnt;
-    uint32_t *ctr;
     int64_t sbase, nstride, S, t0;
     Key2 key;
     double fx_scale;
@@ -935,6 +903,45 @@ struct SplitCtx {
     uint32_t nbh, full, lmask;
     bool sample;
 };
+
+// Mailboxes of the exchange.  Every exchanged value carries a 2-bit tag, the
+// sweep's tag 1 + (s mod 2) for local sweep s, and a reader waits until the
+// word it loaded carries the tag of the sweep it is in; the buffers are
+// zeroed (tag 0) before every launch.  A slot holds the value of sweep s - 1
+// or s when a reader of sweep s looks at it, never s + 1: a member publishes
+// the values of sweep s + 1 only after it has read every owner's new values
+// of sweep s, which each owner publishes after it has read the slots (every
+// member owns at least one variable group).  So one tag bit of history is
+// enough, and the words themselves replace a counter barrier.
+//   partial logit x (|x| < 2^61, bits 61..63 equal): x ^ (tag << 61)
+//   partial count c (< 2^29): c | tag << 29
+//   new values of a group: v0 | v1 << 8 | v2 << 16 | v3 << 24 | tag << 1
+constexpr uint32_t kMailSpins = 1u << 20;   // ~1 s of waiting before giving up
+constexpr int32_t kCntMask = (1 << 29) - 1;
+
+__device__ __forceinline__ uint32_t tag_x(int64_t e) {
+    const uint64_t u = (uint64_t)e;
+    return (uint32_t)((u >> 61) & 3u) ^ (uint32_t)((u >> 63) * 3u);
+}
+__device__ __forceinline__ uint32_t tag_c(int32_t e) { return ((uint32_t)e >> 29) & 3u; }
+__device__ __forceinline__ uint32_t tag_v(uint32_t w) { return (w >> 1) & 3u; }
+
+// Reload *p until its tag is `want` (bounded: on time-out the error flag is
+// raised and the stale word returned; once the flag is up nobody waits).
+template <typename T, typename TagOf>
+__device__ __forceinline__ T await_tag(const T *p, T e, uint32_t want, TagOf tag_of, int32_t *err) {
+    uint32_t spins = 0;
+    while (tag_of(e) != want) {
+        __builtin_amdgcn_s_sleep(1);
+        e = xload(p);
+        if (++spins > kMailSpins) {
+            xstore(err, 1);
+            break;
+        }
+        if ((spins & 1023u) == 0u && xload(err)) break;
+    }
+    return e;
+}
 
 // The sweeps of one member.  Member g owns variable groups [q_lo, q_hi) (of
 // 4): it keeps its own partial logits of those in LDS, publishes the others,
@@ -947,7 +954,7 @@ struct SplitCtx {
 template <typename Real, int VPT, bool kClust>
 __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const SplitParams &Q, const SplitCtx<Real> &c,
                                              Real (&nu)[VPT > 0 ? VPT : 1], const int32_t (&ncr)[VPT > 0 ? VPT : 1],
-                                             int &smax, uint32_t &phase) {
+                                             int &smax) {
     const PushLds &L = c.L;
     const int G = c.G, g = c.g, N = c.N, tid = c.tid, NT = c.NT;
     const int own_lo = c.q_lo * 4, own_hi = min(N, c.q_hi * 4);
@@ -955,6 +962,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
     for (int64_t s = 0; s < c.S; ++s) {
         const uint64_t t = (uint64_t)(c.t0 + s);
         const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+        const uint32_t tag = 1u + (uint32_t)(s & 1);
         // member g's records: every G-th of the length-sorted order (the same
         // mix of clause lengths for all members), stored as one contiguous run
         const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, tlo, thi,
@@ -966,14 +974,13 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         if (c.sample) {
             for (int i = tid; i < N; i += NT) {
                 if (i >= own_lo && i < own_hi) continue;
-                xstore(&c.xpart[(size_t)g * c.nstride + i], L.x[i]);
+                xstore(&c.xpart[(size_t)g * c.nstride + i], L.x[i] ^ ((int64_t)tag << 61));
                 L.x[i] = 0;
             }
         }
-        if (tid == 0) xstore(&c.pcnt[g], part);
-        group_barrier(c.ctr, ++phase * (uint32_t)G, Q.err);
+        if (tid == 0) xstore(&c.pcnt[g], (int32_t)((uint32_t)part | (tag << 29)));
         int total = 0;
-        for (int k = 0; k < G; ++k) total += xload(&c.pcnt[k]);
+        for (int k = 0; k < G; ++k) total += await_tag(&c.pcnt[k], xload(&c.pcnt[k]), tag, tag_c, Q.err) & kCntMask;
         const bool improved = total > smax;
         if (improved) smax = total;
         // visible phase on the owned variables
@@ -991,7 +998,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                         const int q = i & 3;
                         const uint32_t word = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
                         // the partials of the other members: a batch of loads
-                        // in flight before any is used
+                        // in flight before any is waited for
                         int64_t xs = (int64_t)(VPT > 0 ? ncr[j] : c.negcnt[i]) + L.x[i];
                         L.x[i] = 0;
                         for (int k0 = 0; k0 < G; k0 += 4) {
@@ -999,10 +1006,16 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
 #pragma unroll
                             for (int kk = 0; kk < 4; ++kk) {
                                 const int k = k0 + kk;
-                                pk[kk] = (k < G && k != g) ? xload(&c.xpart[(size_t)k * c.nstride + i]) : 0;
+                                pk[kk] = (k < G && k != g) ? xload(&c.xpart[(size_t)k * c.nstride + i])
+                                                           : ((int64_t)tag << 61);
                             }
 #pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) xs += pk[kk];
+                            for (int kk = 0; kk < 4; ++kk) {
+                                const int k = k0 + kk;
+                                if (k < G && k != g)
+                                    pk[kk] = await_tag(&c.xpart[(size_t)k * c.nstride + i], pk[kk], tag, tag_x, Q.err);
+                                xs += pk[kk] ^ ((int64_t)tag << 61);
+                            }
                         }
                         if (VPT > 0) {
                             nvb = visible_update(xs, c.fx_scale, nu[j], c.alpha, word);
@@ -1018,18 +1031,18 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                     // own_lo and NT are multiples of 4: thread tid holds word i & 3 = tid & 3
                     const uint32_t b1 = __shfl_down(nvb, 1, kWave), b2 = __shfl_down(nvb, 2, kWave),
                                    b3 = __shfl_down(nvb, 3, kWave);
-                    if (act && (tid & 3) == 0) xstore(&c.vbuf[i >> 2], nvb | (b1 << 8) | (b2 << 16) | (b3 << 24));
+                    if (act && (tid & 3) == 0)
+                        xstore(&c.vbuf[i >> 2], nvb | (b1 << 8) | (b2 << 16) | (b3 << 24) | (tag << 1));
                 }
             }
         }
         if (c.sample) {
-            group_barrier(c.ctr, ++phase * (uint32_t)G, Q.err);
             for (int q = tid; q < c.groups; q += NT) {
                 if (q >= c.q_lo && q < c.q_hi) continue;
-                const uint32_t word = xload(&c.vbuf[q]);
+                const uint32_t word = await_tag(&c.vbuf[q], xload(&c.vbuf[q]), tag, tag_v, Q.err);
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (q * 4 + k < N) L.v[q * 4 + k] = (uint8_t)(word >> (8 * k));
+                    if (q * 4 + k < N) L.v[q * 4 + k] = (uint8_t)((word >> (8 * k)) & 1u);
             }
             __syncthreads();
         }
@@ -1083,17 +1096,15 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.fx_scale = P.fx_scale;
     c.negcnt = P.negcnt + fd.var_off;
     c.nstride = Q.nstride;
-    // this member's owned variable groups (of 4)
+    // this member's owned variable groups (of 4): a balanced partition, at
+    // least one group each (the plan admits a split only if groups >= G)
     c.groups = (N + 3) >> 2;
-    const int gg = (c.groups + G - 1) / G;
-    c.q_lo = min(c.groups, g * gg);
-    c.q_hi = min(c.groups, c.q_lo + gg);
+    c.q_lo = (int)((int64_t)g * c.groups / G);
+    c.q_hi = (int)((int64_t)(g + 1) * c.groups / G);
     // exchange buffers of this item (each starts on its own 128-byte line)
     c.xpart = Q.xpart + (size_t)item * G * Q.nstride;
     c.vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
     c.pcnt = Q.cnt + (size_t)item * kMaxSplit;
-    c.ctr = Q.bar + (size_t)item * 32;
-    uint32_t phase = 0;
 
     load_push_tables<false, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
@@ -1115,7 +1126,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.t0 = *P.t_ptr;
     __syncthreads();
 
-    split_sweeps<Real, VPT, kClust>(P, Q, c, nu, ncr, smax, phase);
+    split_sweeps<Real, VPT, kClust>(P, Q, c, nu, ncr, smax);
 
     // write back the owned part of the state
     for (int i = own_lo + tid; i < own_hi; i += NT) P.v[c.sbase + i] = L.v[i];
@@ -1333,13 +1344,15 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     Q.xpart = p.d_xpart;
     Q.vbuf = p.d_vbuf;
     Q.cnt = p.d_cnt;
-    Q.bar = p.d_bar;
     Q.err = p.d_err;
     Q.nstride = p.nstride;
     Q.G = p.split;
     Q.xcd_map = p.xcd_map;
     Q.n_xcd = 8;
-    hipError_t e = launch_zero(p.d_bar, (int64_t)b.count * 32, s);
+    // every mailbox starts with tag 0 (no sweep's tag)
+    hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(p.d_xpart), (int64_t)b.count * p.split * p.nstride * 2, s);
+    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_vbuf), (int64_t)b.count * p.nstride / 4, s);
+    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_cnt), (int64_t)b.count * kMaxSplit, s);
     if (e != hipSuccess) return e;
     const int groups = (b.max_n + 3) / 4;
     const int owned = 4 * ((groups + p.split - 1) / p.split);   // variables per member

@@ -330,21 +330,25 @@ def test_split_two_owned_variables_per_thread(hip, prec):
 
 
 def test_split_tiny_ragged_members(hip):
-    """Members that own no variables or no clauses."""
-    clauses = [[[5, -1, 2], [-3, 4], [1], [-5, 2, 3]], [[1, -2], [2]]]
+    """Members that own a single variable group and members with no clauses;
+    a split that would leave a member without variables is refused."""
+    from paper_2311_02101_amd import hp
+    clauses = [[[5, -1, 2], [-3, 4], [29, 1]], [[1, -2], [33, 2]]]
     tables = [wl.pad_clauses(cl, 3) for cl in clauses]
     W, b = wl.gaussian_rbm(1, 3, 3, 6)
-    say("[split tiny] N=5,2 split 8")
-    ref, _ = _run_states(tables, [5, 2], W, b, 8, 25, "f64", 6, split=1)
-    got, _ = _run_states(tables, [5, 2], W, b, 8, 25, "f64", 6, split=8)
+    say("[split tiny] N=29,33 split 8")
+    ref, _ = _run_states(tables, [29, 33], W, b, 8, 25, "f64", 6, split=1)
+    got, _ = _run_states(tables, [29, 33], W, b, 8, 25, "f64", 6, split=8)
     _same(ref, got)
+    with pytest.raises(hp.HpError):
+        hp.Plan(tables, [29, 5], W, b, chains=8, split=8)
 
 
 @pytest.mark.parametrize("split,chains", [(2, 16), (4, 8), (16, 2)])
 def test_split_small_formulas_many_sweeps(hip, split, chains):
     """Small exchanges repeated over many sweeps: the exchanged lines stay in
-    the CUs' vector caches unless each barrier invalidates them."""
-    sizes = [37, 64, 90, 127, 11, 50, 77, 100]     # one size class: one launch
+    the CUs' vector caches unless every exchange access bypasses them."""
+    sizes = [67, 64, 90, 127, 61, 80, 77, 100]     # one size class (one launch), > 4 (16 - 1) each
     tables = [wl.random_formula(n, 9, tag=f) for f, n in enumerate(sizes)]
     W, b = wl.gaussian_rbm(2, 7, 8, 9)
     say(f"[split small] sizes={sizes} split={split} chains={chains} 300 sweeps")
