@@ -654,7 +654,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         const size_t items = (size_t)p->buckets[0].count;
         HP_TRY(hipMalloc((void **)&p->d_xpart, items * p->split * p->nstride * sizeof(int64_t)), "alloc xpart");
         HP_TRY(hipMalloc((void **)&p->d_vbuf, items * p->nstride), "alloc vbuf");
-        HP_TRY(hipMalloc((void **)&p->d_cnt, items * kMaxSplit * sizeof(int32_t)), "alloc counts");
+        HP_TRY(hipMalloc((void **)&p->d_cnt, items * 2 * kMaxSplit * sizeof(int32_t)), "alloc counts");
     }
     HP_TRY(launch_tables(*p, s), "table kernel");
     // host staging vectors go out of scope below: wait for the copies

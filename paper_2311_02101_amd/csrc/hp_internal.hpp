@@ -139,7 +139,7 @@ constexpr int kMaxSplit = 16;
 struct SplitParams {
     int64_t *xpart;              // [items][G][nstride]
     uint8_t *vbuf;               // [items][nstride]
-    int32_t *cnt;                // [items][kMaxSplit] partial clause counts (64 bytes)
+    int32_t *cnt;                // [items][2][kMaxSplit] partial clause counts by sweep parity
     int32_t *err;                // [1] exchange time-out flag
     int64_t nstride;
     int32_t G;

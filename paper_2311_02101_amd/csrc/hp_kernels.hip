@@ -907,12 +907,16 @@ struct SplitCtx {
 // Mailboxes of the exchange.  Every exchanged value carries a 2-bit tag, the
 // sweep's tag 1 + (s mod 2) for local sweep s, and a reader waits until the
 // word it loaded carries the tag of the sweep it is in; the buffers are
-// zeroed (tag 0) before every launch.  A slot holds the value of sweep s - 1
-// or s when a reader of sweep s looks at it, never s + 1: a member publishes
-// the values of sweep s + 1 only after it has read every owner's new values
-// of sweep s, which each owner publishes after it has read the slots (every
-// member owns at least one variable group).  So one tag bit of history is
-// enough, and the words themselves replace a counter barrier.
+// zeroed (tag 0) before every launch.  A partial-logit or new-value slot
+// holds the value of sweep s - 1 or s when a reader of sweep s looks at it,
+// never s + 1: a member publishes the values of sweep s + 1 only after it has
+// read every owner's new values of sweep s, which each owner publishes after
+// it has read the partials (every member owns at least one variable group).
+// The partial counts may be read after the new values are published, so they
+// alternate between two slots by sweep parity and carry the tag
+// 1 + (s div 2 mod 2): a slot is rewritten two sweeps later, only after every
+// reader has passed the sweep in between.  The words themselves replace a
+// counter barrier.
 //   partial logit x (|x| < 2^61, bits 61..63 equal): x ^ (tag << 61)
 //   partial count c (< 2^29): c | tag << 29
 //   new values of a group: v0 | v1 << 8 | v2 << 16 | v3 << 24 | tag << 1
@@ -978,11 +982,26 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                 L.x[i] = 0;
             }
         }
-        if (tid == 0) xstore(&c.pcnt[g], (int32_t)((uint32_t)part | (tag << 29)));
-        int total = 0;
-        for (int k = 0; k < G; ++k) total += await_tag(&c.pcnt[k], xload(&c.pcnt[k]), tag, tag_c, Q.err) & kCntMask;
-        const bool improved = total > smax;
-        if (improved) smax = total;
+        int32_t *const pc = c.pcnt + (s & 1) * kMaxSplit;
+        const uint32_t ctag = 1u + (uint32_t)((s >> 1) & 1);
+        if (tid == 0) xstore(&pc[g], (int32_t)((uint32_t)part | (ctag << 29)));
+        // the total count decides whether the counted state becomes the best;
+        // with the owned variables' old values kept in registers (VPT > 0)
+        // that wait moves behind the visible phase, off the critical path
+        constexpr bool kLateCount = VPT > 0;
+        auto await_total = [&]() {
+            int total = part;
+            for (int k = 0; k < G; ++k)
+                if (k != g) total += await_tag(&pc[k], xload(&pc[k]), ctag, tag_c, Q.err) & kCntMask;
+            return total;
+        };
+        bool improved = false;
+        if (!kLateCount || !c.sample) {
+            const int total = await_total();
+            improved = total > smax;
+            if (improved) smax = total;
+        }
+        uint8_t oldv[VPT > 0 ? VPT : 1];
         // visible phase on the owned variables
 #pragma unroll
         for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
@@ -990,6 +1009,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                 const int i = own_lo + tid + jj * NT;
                 const bool act = i < own_hi;
                 uint32_t nvb = 0;
+                if (VPT > 0) oldv[j] = act ? L.v[i] : 0;
                 if (act) {
                     if (improved) P.best[c.sbase + i] = L.v[i];
                     if (c.sample) {
@@ -1033,6 +1053,17 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                                    b3 = __shfl_down(nvb, 3, kWave);
                     if (act && (tid & 3) == 0)
                         xstore(&c.vbuf[i >> 2], nvb | (b1 << 8) | (b2 << 16) | (b3 << 24) | (tag << 1));
+                }
+            }
+        }
+        if (kLateCount && c.sample) {
+            const int total = await_total();
+            if (total > smax) {
+                smax = total;
+#pragma unroll
+                for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
+                    const int i = own_lo + tid + j * NT;
+                    if (i < own_hi) P.best[c.sbase + i] = oldv[j];
                 }
             }
         }
@@ -1104,7 +1135,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     // exchange buffers of this item (each starts on its own 128-byte line)
     c.xpart = Q.xpart + (size_t)item * G * Q.nstride;
     c.vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
-    c.pcnt = Q.cnt + (size_t)item * kMaxSplit;
+    c.pcnt = Q.cnt + (size_t)item * 2 * kMaxSplit;
 
     load_push_tables<false, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
@@ -1352,7 +1383,7 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     // every mailbox starts with tag 0 (no sweep's tag)
     hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(p.d_xpart), (int64_t)b.count * p.split * p.nstride * 2, s);
     if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_vbuf), (int64_t)b.count * p.nstride / 4, s);
-    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_cnt), (int64_t)b.count * kMaxSplit, s);
+    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_cnt), (int64_t)b.count * 2 * kMaxSplit, s);
     if (e != hipSuccess) return e;
     const int groups = (b.max_n + 3) / 4;
     const int owned = 4 * ((groups + p.split - 1) / p.split);   // variables per member
