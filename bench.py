@@ -33,11 +33,14 @@ if ROOT not in sys.path:
 #   one call = 10 rounds x (2 v_mad_u64_u32 + 2 three-input XORs, gfx950's
 #            v_bitop3_b32) = 40 VALU instructions, each one issue slot per
 #            lane (a Philox-only loop with 2-input XORs measures 55 lane-slots
-#            per call for its ~58 instructions at the rated clock)
+#            per call for its ~58 instructions at the rated clock), less the
+#            3 of the first two rounds that depend only on the counter words
+#            shared by a whole chain-sweep (computed once per chain-sweep):
+#            37 per call
 #   each Bernoulli draw adds a shift and an unsigned compare (2 slots)
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-slots/s.
 # ---------------------------------------------------------------------------
-PHILOX_SLOTS = 40
+PHILOX_SLOTS = 37
 DRAW_SLOTS = 2
 PEAK_SLOTS = 256 * 64 * 2.4e9
 MFMA_BF16_PEAK = 2.5e15          # dense BF16 MFMA, MI355X

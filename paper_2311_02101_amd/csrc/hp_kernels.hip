@@ -192,36 +192,38 @@ size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, i
     return off;
 }
 
-// push LDS layout: thr (4 KB) | gfx (16 KB) | gpad (16 KB) | counts | x (8 B/var) | v (1 B/var)
+// push LDS layout: thr (4 KB) | gfx (16 KB) | gpad (16 KB) | counts | v (1 B/var) | x (8 B/var)
 constexpr int kPushGfxOff = kPatterns * kMaxL * 4;
 constexpr int kPushGpadOff = kPushGfxOff + kHidMasks * kMaxL * 8;
 constexpr int kPushCntOff = kPushGpadOff + kMaxL * kHidMasks * 8;
-constexpr int kPushXOff = kPushCntOff + 64 * 4;
+constexpr int kPushVOff = kPushCntOff + 64 * 4;
 
-// wide layout (G tables read from global memory): thr | counts | x | v
+// wide layout (G tables read from global memory): thr | counts | v | x
 constexpr int kWideCntOff = kPatterns * kMaxL * 4;
-constexpr int kWideXOff = kWideCntOff + 64 * 4;
+constexpr int kWideVOff = kWideCntOff + 64 * 4;
 
-// size-clustered layout: thr (248 rows) | gfx (488 rows) | gpad (504) | counts | x | v
+// size-clustered layout: thr (248 rows) | gfx (488 rows) | gpad (504) | counts | v | x
 constexpr int kClustGfxOff = kClustThrRows * kMaxL * 4;
 constexpr int kClustGpadOff = kClustGfxOff + kClustGfxRows * kMaxL * 8;
 constexpr int kClustCntOff = kClustGpadOff + kClustGpad * 8;
-constexpr int kClustXOff = kClustCntOff + 64 * 4;
+constexpr int kClustVOff = kClustCntOff + 64 * 4;
 
+// v sits at a fixed offset (below 64 KB), so a gather is one LDS read with
+// the offset in the instruction; x follows, 16-byte aligned
 static size_t lds_tail(size_t off, int max_n, int32_t *v_off, int32_t *x_off) {
-    *x_off = (int32_t)off;
-    off += (size_t)max_n * 8;
     *v_off = (int32_t)off;
     off += ((size_t)max_n + 15) / 16 * 16;
+    *x_off = (int32_t)off;
+    off += (size_t)max_n * 8;
     return off;
 }
 
 size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off) {
-    return lds_tail(wide ? kWideXOff : kPushXOff, max_n, v_off, x_off);
+    return lds_tail(wide ? kWideVOff : kPushVOff, max_n, v_off, x_off);
 }
 
 size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off) {
-    return lds_tail(kClustXOff, max_n, v_off, x_off);
+    return lds_tail(kClustVOff, max_n, v_off, x_off);
 }
 
 // Hidden draw of one clause: L Bernoulli bits against the pre-shifted
@@ -236,18 +238,18 @@ __device__ __forceinline__ uint32_t draw4(const uint4 &r, const uint4 &t) {
     return n + n + (uint32_t)(r.x <= t.x);
 }
 
-__device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t tlo, uint32_t thi,
-                                                uint32_t chain, uint32_t blk, Key2 key, uint32_t nbh) {
+__device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t blk, const PhiloxSweep &u, Key2 key,
+                                                uint32_t nbh) {
     const uint4 ta = *reinterpret_cast<const uint4 *>(row);
-    uint4 ra = make_uint4(tlo, chain, kPhaseHidden | blk, thi);
     if (nbh > 1) {
         // both blocks in one pass (interleaved rounds, one key schedule)
         const uint4 tb = *reinterpret_cast<const uint4 *>(row + 4);
-        uint4 rb = make_uint4(tlo, chain, kPhaseHidden | (blk + 1u), thi);
-        philox4x32_10_pair(ra, rb, key);
-        return draw4(ra, ta) | (draw4(rb, tb) << 4);
+        uint4 r[2];
+        const uint32_t w[2] = {kPhaseHidden | blk, kPhaseHidden | (blk + 1u)};
+        philox_sweep_multi<2>(r, w, u, key);
+        return draw4(r[0], ta) | (draw4(r[1], tb) << 4);
     }
-    return draw4(philox4x32_10(ra, key), ta);
+    return draw4(philox_sweep(kPhaseHidden | blk, u, key), ta);
 }
 
 // VPT > 0: each thread owns VPT groups of 4 consecutive variables and keeps
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(1024) void sweep_pull_kernel(SweepParams<Real> P) {
 
     for (int64_t s = 0; s < S; ++s) {
         const uint64_t t = (uint64_t)(t0 + s);
-        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+        const PhiloxSweep ps = philox_sweep_consts((uint32_t)t, (uint32_t)w.b, (uint32_t)(t >> 32), key);
         // ---- clause phase: gather, count, hidden draw ----
         int cnt = 0;
         for (int c = tid; c < C; c += NT) {
@@ -315,8 +317,7 @@ __global__ __launch_bounds__(1024) void sweep_pull_kernel(SweepParams<Real> P) {
             }
             cnt += (m != 0u);
             if (sample) {
-                uint32_t n = hidden_mask(s_thr + m * kMaxL, tlo, thi, (uint32_t)w.b, (uint32_t)c * nbh, key,
-                                         nbh) & lmask;
+                uint32_t n = hidden_mask(s_thr + m * kMaxL, (uint32_t)c * nbh, ps, key, nbh) & lmask;
                 s_hm[c] = (uint8_t)n;
             }
         }
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(1024) void sweep_pull_kernel(SweepParams<Real> P) {
             const int grp = tid + jj * NT;
             if (grp < groups) {
                 uint4 r = make_uint4(0, 0, 0, 0);
-                if (sample) r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseVisible | (uint32_t)grp, thi), key);
+                if (sample) r = philox_sweep(kPhaseVisible | (uint32_t)grp, ps, key);
                 const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -403,25 +404,25 @@ struct PushLds {
     uint8_t *v;
 };
 
-__device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off, int v_off) {
+__device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off) {
     return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kPushGfxOff),
                    reinterpret_cast<int64_t *>(lds + kPushGpadOff), reinterpret_cast<int *>(lds + kPushCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds + v_off};
+                   reinterpret_cast<int64_t *>(lds + x_off), lds + kPushVOff};
 }
 
 // wide variant: the G tables of temperature tau stay in global memory
-__device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, int v_off, const int64_t *gfx,
+__device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, const int64_t *gfx,
                                                  const int64_t *gpad, int tau) {
     return PushLds{reinterpret_cast<uint32_t *>(lds), const_cast<int64_t *>(gfx + tau * kHidMasks * kMaxL),
                    const_cast<int64_t *>(gpad + tau * kHidMasks * kMaxL),
                    reinterpret_cast<int *>(lds + kWideCntOff), reinterpret_cast<int64_t *>(lds + x_off),
-                   lds + v_off};
+                   lds + kWideVOff};
 }
 
-__device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off, int v_off) {
+__device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off) {
     return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kClustGfxOff),
                    reinterpret_cast<int64_t *>(lds + kClustGpadOff), reinterpret_cast<int *>(lds + kClustCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds + v_off};
+                   reinterpret_cast<int64_t *>(lds + x_off), lds + kClustVOff};
 }
 
 template <bool kWide, bool kClust = false>
@@ -501,8 +502,8 @@ __device__ __forceinline__ void scatter_any(int64_t *x, const uint4 &r, uint32_t
 template <bool kSample, bool kClust = false>
 __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
                                             const uint32_t *__restrict__ orig, int c_first, int c_step,
-                                            int c_end, int tid, int NT, uint32_t tlo, uint32_t thi, uint32_t chain,
-                                            Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
+                                            int c_end, int tid, int NT, const PhiloxSweep &ps, Key2 key,
+                                            uint32_t nbh, uint32_t full, uint32_t lmask) {
     int cnt = 0;
     uint4 r_next = make_uint4(0, 0, 0, 0);
     uint32_t o_next = 0;
@@ -549,13 +550,13 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
             if (kClust) {
                 const uint32_t Kc = len < 3u ? 3u : len;
                 const bool big = Kc > 3u;                            // L = K + 1 > 4: two blocks
-                n = hidden_mask(L.thr + ((1u << Kc) - 8u + m) * kMaxL, tlo, thi, chain, oc * 2u, key,
+                n = hidden_mask(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc * 2u, ps, key,
                                 big ? 2u : 1u) &
                     (big ? (2u << Kc) - 1u : 7u);
                 g0 = L.gpad[(len <= 3u ? 8u * (len - 1u) : (2u << len) - 8u) + n];
                 gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
             } else {
-                n = hidden_mask(L.thr + m * kMaxL, tlo, thi, chain, oc * nbh, key, nbh) & lmask;
+                n = hidden_mask(L.thr + m * kMaxL, oc * nbh, ps, key, nbh) & lmask;
                 g0 = L.gpad[len * kHidMasks + n];
                 gr = L.gfx + n * kMaxL;
             }
@@ -751,9 +752,9 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         const FormulaDev fd = P.fd[w.f];
         const int N = fd.n, C = fd.c;
         const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
-        const PushLds L = kClust ? push_lds_clust(lds, P.lds_x_off, P.lds_v_off)
-                          : kWide ? push_lds_wide(lds, P.lds_x_off, P.lds_v_off, P.gfx, P.gpad, tau)
-                                  : push_lds(lds, P.lds_x_off, P.lds_v_off);
+        const PushLds L = kClust ? push_lds_clust(lds, P.lds_x_off)
+                          : kWide ? push_lds_wide(lds, P.lds_x_off, P.gfx, P.gpad, tau)
+                                  : push_lds(lds, P.lds_x_off);
         const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
         const uint4 *__restrict__ rec = P.rec + fd.clause_off;
         const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
@@ -789,6 +790,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         for (int64_t s = 0; s < S; ++s) {
             const uint64_t t = (uint64_t)(t0 + s);
             const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+            const PhiloxSweep ps = philox_sweep_consts(tlo, (uint32_t)w.b, thi, key);
             int cnt;
             if (kMfma)
                 cnt = sample ? clause_phase_mfma<true>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh, full,
@@ -796,10 +798,8 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
                              : clause_phase_mfma<false>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh,
                                                         full, lmask, P.K, a1, a2, 1.0 / fx_scale);
             else
-                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key,
-                                                          nbh, full, lmask)
-                             : clause_phase<false, kClust>(L, rec, orig, 0, 1, C, tid, NT, tlo, thi, (uint32_t)w.b, key,
-                                                           nbh, full, lmask);
+                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, 0, 1, C, tid, NT, ps, key, nbh, full, lmask)
+                             : clause_phase<false, kClust>(L, rec, orig, 0, 1, C, tid, NT, ps, key, nbh, full, lmask);
             const int total = block_total(L, cnt, tid, NT);
             const bool improved = total > smax;
             if (improved) smax = total;
@@ -812,7 +812,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
                 const int grp = tid + jj * NT;
                 if (grp < groups) {
                     uint4 r = make_uint4(0, 0, 0, 0);
-                    if (sample) r = philox4x32_10(make_uint4(tlo, (uint32_t)w.b, kPhaseVisible | (uint32_t)grp, thi), key);
+                    if (sample) r = philox_sweep(kPhaseVisible | (uint32_t)grp, ps, key);
                     const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -969,10 +969,11 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         const uint32_t tag = 1u + (uint32_t)(s & 1);
         // member g's records: every G-th of the length-sorted order (the same
         // mix of clause lengths for all members), stored as one contiguous run
-        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, tlo, thi,
-                                                              (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask)
-                                 : clause_phase<false, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, tlo,
-                                                               thi, (uint32_t)c.b, c.key, c.nbh, c.full, c.lmask);
+        const PhiloxSweep ps = philox_sweep_consts(tlo, (uint32_t)c.b, thi, c.key);
+        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, ps, c.key,
+                                                              c.nbh, c.full, c.lmask)
+                                 : clause_phase<false, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, ps, c.key,
+                                                               c.nbh, c.full, c.lmask);
         const int part = block_total(L, cnt, tid, NT);
         // publish the partial logits of the variables other members own
         if (c.sample) {
@@ -1013,8 +1014,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                 if (act) {
                     if (improved) P.best[c.sbase + i] = L.v[i];
                     if (c.sample) {
-                        const uint4 r =
-                            philox4x32_10(make_uint4(tlo, (uint32_t)c.b, kPhaseVisible | (uint32_t)(i >> 2), thi), c.key);
+                        const uint4 r = philox_sweep(kPhaseVisible | (uint32_t)(i >> 2), ps, c.key);
                         const int q = i & 3;
                         const uint32_t word = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
                         // the partials of the other members: a batch of loads
@@ -1084,7 +1084,7 @@ template <typename Real, int VPT, bool kClust = false>
 __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, SplitParams Q) {
     extern __shared__ __align__(16) unsigned char lds[];
     SplitCtx<Real> c;
-    c.L = kClust ? push_lds_clust(lds, P.lds_x_off, P.lds_v_off) : push_lds(lds, P.lds_x_off, P.lds_v_off);
+    c.L = kClust ? push_lds_clust(lds, P.lds_x_off) : push_lds(lds, P.lds_x_off);
     const PushLds &L = c.L;
 
     // workgroup -> (item, member g); with the XCD map the G members of an
