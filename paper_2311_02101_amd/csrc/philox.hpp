@@ -41,28 +41,6 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key2 key) {
     return x;
 }
 
-// Two counters under one key, round by round: the two chains of dependent
-// multiplies interleave and the key schedule is computed once.
-__device__ __forceinline__ void philox4x32_10_pair(uint4 &x, uint4 &y, Key2 key) {
-    uint32_t k0 = key.k0, k1 = key.k1;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            asm volatile("" : "+s"(k0), "+s"(k1));
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x.x;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x.z;
-        const uint64_t q0 = (uint64_t)0xD2511F53u * (uint64_t)y.x;
-        const uint64_t q1 = (uint64_t)0xCD9E8D57u * (uint64_t)y.z;
-        x = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x.y, k0, 0x96), (uint32_t)p1,
-                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x.w, k1, 0x96), (uint32_t)p0);
-        y = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(q1 >> 32), y.y, k0, 0x96), (uint32_t)q1,
-                       __builtin_amdgcn_bitop3_b32((uint32_t)(q0 >> 32), y.w, k1, 0x96), (uint32_t)q0);
-    }
-}
-
 // Same generator for a key that differs between lanes (kept in vector
 // registers; no scalar-register pinning).
 __device__ __forceinline__ uint4 philox4x32_10_lane_key(uint4 x, Key2 key) {
