@@ -91,11 +91,12 @@ void release(Plan *p) {
 
 
 // Variable groups (of 4) per thread whose variance EMA stays in registers:
-// 1 or 2, else 0 (EMA in global memory).  The mixed-precision kernel keeps
-// at most one group in registers (two spill next to its MFMA operands).
-int vpt_for(int groups, int threads, bool mixed) {
+// 1 or 2, else 0 (EMA in global memory).  The mixed-precision kernel and the
+// FP64 kernels keep at most one group in registers (two spill: the FP64 push
+// kernel measured 1.2% faster with the EMA of two groups in global memory).
+int vpt_for(int groups, int threads, bool mixed, bool fp64) {
     if (groups <= threads) return 1;
-    if (groups <= 2 * threads && !mixed) return 2;
+    if (groups <= 2 * threads && !mixed && !fp64) return 2;
     return 0;
 }
 
@@ -498,7 +499,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         }
         bk.threads = t;
         const int groups = (bk.max_n + 3) / 4;
-        bk.vpt = vpt_for(groups, t, mixed);
+        bk.vpt = vpt_for(groups, t, mixed, opts->precision != HP_FP32);
         // persistent grid when the items outnumber the resident workgroups
         const int occ = bucket_occupancy(*p, bk);
         const int64_t capacity = (int64_t)p->cus * std::max(occ, 1);
@@ -741,7 +742,7 @@ hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *st
             bk = orig;
             bk.threads = t;
             const int groups = (bk.max_n + 3) / 4;
-            bk.vpt = vpt_for(groups, t, p->precision == HP_MIXED_BF16);
+            bk.vpt = vpt_for(groups, t, p->precision == HP_MIXED_BF16, p->precision != HP_FP32);
             const int occ = bucket_occupancy(*p, bk);
             if (occ < 1) continue;     // this shape cannot launch
             const int64_t capacity = (int64_t)p->cus * occ;
