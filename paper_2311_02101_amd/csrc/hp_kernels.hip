@@ -990,11 +990,14 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         // with the owned variables' old values kept in registers (VPT > 0)
         // that wait moves behind the visible phase, off the critical path
         constexpr bool kLateCount = VPT > 0;
+        // lane k < G of every wave fetches member k's count and the wave sums
+        // them (one load per member and wave, not per thread)
         auto await_total = [&]() {
-            int total = part;
-            for (int k = 0; k < G; ++k)
-                if (k != g) total += await_tag(&pc[k], xload(&pc[k]), ctag, tag_c, Q.err) & kCntMask;
-            return total;
+            const int lane = tid & (kWave - 1);
+            int mine = 0;
+            if (lane < G)
+                mine = lane == g ? part : (await_tag(&pc[lane], xload(&pc[lane]), ctag, tag_c, Q.err) & kCntMask);
+            return wave_sum(mine);
         };
         bool improved = false;
         if (!kLateCount || !c.sample) {
