@@ -60,3 +60,23 @@ def test_temperature_split():
     assert list(wl.default_temperatures(3, 2)) == [0, 0, 1]
     assert list(wl.default_temperatures(1, 1)) == [0]
     assert wl.hidden_units_for(3) == 3 and wl.hidden_units_for(7) == 8
+
+
+def test_bench_work_model_of_the_clustered_model():
+    """bench.py's ALU model for the size-clustered model: clause lengths as the
+    oracle reads them, one Philox block and 3 draws for lengths <= 3, two
+    blocks and len + 1 draws above, plus the visible groups."""
+    import bench
+    from oracle import clustered as CL
+    n = 300
+    T = wl.random_formula(n, 5, lengths=[1, 2, 3, 4, 7], probs=[0.2, 0.3, 0.2, 0.15, 0.15])
+    lens = bench.clause_lengths(T)
+    assert np.array_equal(lens, CL.clause_lengths(T, n))
+    calls, draws, slots = bench.chain_sweep_work_clustered(n, T)
+    big = lens > 3
+    assert calls == int(np.sum(np.where(big, 2, 1))) + (n + 3) // 4
+    assert draws == int(np.sum(np.where(big, lens + 1, 3))) + n
+    assert slots == calls * bench.PHILOX_SLOTS + draws * bench.DRAW_SLOTS
+    # the padded model: every clause draws L = 8 units from two blocks
+    c2, d2, _ = bench.chain_sweep_work(n, T.shape[1], 8)
+    assert c2 == 2 * T.shape[1] + (n + 3) // 4 and d2 == 8 * T.shape[1] + n
