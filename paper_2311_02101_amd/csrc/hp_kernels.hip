@@ -394,6 +394,15 @@ __device__ __forceinline__ void push_add(int64_t *s_x, uint32_t e, int64_t g) {
     atomicAdd(reinterpret_cast<unsigned long long *>(&s_x[e & 0x7fffu]), (unsigned long long)g ^ sm);
 }
 
+// The gathers read v through a pointer made from its constant byte offset in
+// the workgroup's dynamic LDS (the sweep kernels have no static LDS, so it
+// starts at 0): the offset folds into the read instruction instead of an add
+// of the array's base address per literal.  (The same form for the tables
+// and accumulators measured slower in the split launch.)
+__device__ __forceinline__ unsigned char *lds_at(int off) {
+    return (unsigned char *)(__attribute__((address_space(3))) unsigned char *)(size_t)off;
+}
+
 // LDS views of the push layout
 struct PushLds {
     uint32_t *thr;
@@ -407,7 +416,7 @@ struct PushLds {
 __device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off) {
     return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kPushGfxOff),
                    reinterpret_cast<int64_t *>(lds + kPushGpadOff), reinterpret_cast<int *>(lds + kPushCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds + kPushVOff};
+                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kPushVOff)};
 }
 
 // wide variant: the G tables of temperature tau stay in global memory
@@ -416,13 +425,13 @@ __device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, 
     return PushLds{reinterpret_cast<uint32_t *>(lds), const_cast<int64_t *>(gfx + tau * kHidMasks * kMaxL),
                    const_cast<int64_t *>(gpad + tau * kHidMasks * kMaxL),
                    reinterpret_cast<int *>(lds + kWideCntOff), reinterpret_cast<int64_t *>(lds + x_off),
-                   lds + kWideVOff};
+                   lds_at(kWideVOff)};
 }
 
 __device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off) {
     return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kClustGfxOff),
                    reinterpret_cast<int64_t *>(lds + kClustGpadOff), reinterpret_cast<int *>(lds + kClustCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds + kClustVOff};
+                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kClustVOff)};
 }
 
 template <bool kWide, bool kClust = false>
