@@ -394,11 +394,11 @@ __device__ __forceinline__ void push_add(int64_t *s_x, uint32_t e, int64_t g) {
     atomicAdd(reinterpret_cast<unsigned long long *>(&s_x[e & 0x7fffu]), (unsigned long long)g ^ sm);
 }
 
-// The gathers read v through a pointer made from its constant byte offset in
-// the workgroup's dynamic LDS (the sweep kernels have no static LDS, so it
-// starts at 0): the offset folds into the read instruction instead of an add
-// of the array's base address per literal.  (The same form for the tables
-// and accumulators measured slower in the split launch.)
+// The gathers and the table reads go through pointers made from constant
+// byte offsets in the workgroup's dynamic LDS (the sweep kernels have no
+// static LDS, so it starts at 0): the offset folds into the read instruction
+// instead of an add of the array's base address per access.  (The same form
+// for the accumulators measured slower in the split launch.)
 __device__ __forceinline__ unsigned char *lds_at(int off) {
     return (unsigned char *)(__attribute__((address_space(3))) unsigned char *)(size_t)off;
 }
@@ -414,8 +414,8 @@ struct PushLds {
 };
 
 __device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off) {
-    return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kPushGfxOff),
-                   reinterpret_cast<int64_t *>(lds + kPushGpadOff), reinterpret_cast<int *>(lds + kPushCntOff),
+    return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kPushGfxOff)),
+                   reinterpret_cast<int64_t *>(lds_at(kPushGpadOff)), reinterpret_cast<int *>(lds + kPushCntOff),
                    reinterpret_cast<int64_t *>(lds + x_off), lds_at(kPushVOff)};
 }
 
@@ -429,8 +429,8 @@ __device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, 
 }
 
 __device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off) {
-    return PushLds{reinterpret_cast<uint32_t *>(lds), reinterpret_cast<int64_t *>(lds + kClustGfxOff),
-                   reinterpret_cast<int64_t *>(lds + kClustGpadOff), reinterpret_cast<int *>(lds + kClustCntOff),
+    return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kClustGfxOff)),
+                   reinterpret_cast<int64_t *>(lds_at(kClustGpadOff)), reinterpret_cast<int *>(lds + kClustCntOff),
                    reinterpret_cast<int64_t *>(lds + x_off), lds_at(kClustVOff)};
 }
 
