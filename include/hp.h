@@ -170,7 +170,9 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
  * "Batching operations").  Each round first counts the satisfied clauses of
  * the current assignment and, on a strict improvement, records it in s_max
  * and best; n_sweeps = 0 performs only that count-and-track step.  *t is
- * advanced by n_sweeps.  HP_EINVAL if the state does not match the plan. */
+ * advanced by n_sweeps.  HP_EINVAL if the state does not match the plan.
+ * Runs of one plan must not overlap in time (a split launch uses the plan's
+ * exchange buffers): issue them on one stream or order them with events. */
 hp_status hp_run(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
 
 /* Autotuner: for every launch of the plan, time each candidate workgroup
