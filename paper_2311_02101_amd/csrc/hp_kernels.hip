@@ -1299,7 +1299,7 @@ hipError_t launch_split_one(const Plan &p, SweepParams<Real> P, SplitParams Q, i
     const Bucket &b = p.buckets[0];
     // The plan checked that all count*G workgroups fit on the device at once
     // (occupancy x CUs), so on an otherwise idle device they are all resident
-    // together; the barrier waits are bounded either way (see hp_check).
+    // together; the waits for the other members are bounded either way (see hp_check).
     hipLaunchKernelGGL((void (*)(SweepParams<Real>, SplitParams))split_kernel_ptr<Real>(p.clust, vpt),
                        dim3(b.count * p.split), dim3(b.threads), b.lds, s, P, Q);
     return hipGetLastError();

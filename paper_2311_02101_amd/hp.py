@@ -252,7 +252,7 @@ class Plan:
                           _stream_handle(stream)))
 
     def check(self):
-        """Synchronise and raise if a device-side barrier timed out."""
+        """Synchronise and raise if a split workgroup timed out waiting for the others."""
         _check(load().hp_check(self._h))
 
     def temper(self, state, parity, stream=None):
