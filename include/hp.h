@@ -119,6 +119,11 @@ typedef struct {
                                        the first literal; hidden unit j of clause c
                                        draws block 2c + j/4.  Push launches only (no
                                        pull kernel, no mixed precision).            */
+    int32_t split_wait_limit;       /* split launches: 0 = wait about a second for
+                                       another workgroup's data before giving up;
+                                       > 0 = reloads of a word before giving up (a
+                                       tiny limit forces the failure path that
+                                       hp_check reports, for tests)                  */
 } hp_opts;
 
 typedef enum {

@@ -231,6 +231,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     if (opts->split < 0 || opts->split > kMaxSplit || (opts->split & (opts->split - 1)))
         return fail(HP_EINVAL, "split must be 0 (automatic) or a power of two up to 16");
     if (opts->graph && opts->split > 1) return fail(HP_EINVAL, "graph mode does not capture split launches");
+    if (opts->split_wait_limit < 0) return fail(HP_EINVAL, "split_wait_limit must be >= 0");
     for (int i = 0; i < T * K * L; ++i)
         if (!std::isfinite(rbm->W[i])) return fail(HP_EINVAL, "non-finite weight");
     for (int i = 0; i < T * L; ++i)
@@ -548,6 +549,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         else bk.grid = 0;                 // split launches run one item per group
     }
     p->split = G;
+    p->wait_limit = opts->split_wait_limit;
     if (G > 1) {
         // member-major record order: member g of a split chain takes every
         // G-th record of the length-sorted order (the same length mix for

@@ -143,6 +143,7 @@ struct SplitParams {
     int32_t *err;                // [1] exchange time-out flag
     int64_t nstride;
     int32_t G;
+    uint32_t wait_limit;         // reloads of a mailbox word before giving up
     int32_t xcd_map;             // members of an item on the same XCD
     int32_t n_xcd;
 };
@@ -182,6 +183,7 @@ struct Plan {
     int32_t cus = 0;             // compute units of the device
     std::vector<Bucket> buckets;
     int32_t split = 1;           // G workgroups per chain (single push bucket only)
+    int32_t wait_limit = 0;      // split: mailbox reloads before giving up (0 = default)
     int32_t xcd_map = 0;
     int64_t nstride = 0;
     int32_t use_graph = 0;

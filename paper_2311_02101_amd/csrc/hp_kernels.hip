@@ -929,7 +929,7 @@ struct SplitCtx {
 //   partial logit x (|x| < 2^61, bits 61..63 equal): x ^ (tag << 61)
 //   partial count c (< 2^29): c | tag << 29
 //   new values of a group: v0 | v1 << 8 | v2 << 16 | v3 << 24 | tag << 1
-constexpr uint32_t kMailSpins = 1u << 20;   // ~1 s of waiting before giving up
+constexpr uint32_t kMailSpins = 1u << 20;   // default limit: ~1 s of waiting before giving up
 constexpr int32_t kCntMask = (1 << 29) - 1;
 
 __device__ __forceinline__ uint32_t tag_x(int64_t e) {
@@ -942,12 +942,13 @@ __device__ __forceinline__ uint32_t tag_v(uint32_t w) { return (w >> 1) & 3u; }
 // Reload *p until its tag is `want` (bounded: on time-out the error flag is
 // raised and the stale word returned; once the flag is up nobody waits).
 template <typename T, typename TagOf>
-__device__ __forceinline__ T await_tag(const T *p, T e, uint32_t want, TagOf tag_of, int32_t *err) {
+__device__ __forceinline__ T await_tag(const T *p, T e, uint32_t want, TagOf tag_of, int32_t *err,
+                                       uint32_t limit) {
     uint32_t spins = 0;
     while (tag_of(e) != want) {
         __builtin_amdgcn_s_sleep(1);
         e = xload(p);
-        if (++spins > kMailSpins) {
+        if (++spins > limit) {
             xstore(err, 1);
             break;
         }
@@ -1005,7 +1006,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
             const int lane = tid & (kWave - 1);
             int mine = 0;
             if (lane < G)
-                mine = lane == g ? part : (await_tag(&pc[lane], xload(&pc[lane]), ctag, tag_c, Q.err) & kCntMask);
+                mine = lane == g ? part : (await_tag(&pc[lane], xload(&pc[lane]), ctag, tag_c, Q.err, Q.wait_limit) & kCntMask);
             return wave_sum(mine);
         };
         bool improved = false;
@@ -1045,7 +1046,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
                             for (int kk = 0; kk < 4; ++kk) {
                                 const int k = k0 + kk;
                                 if (k < G && k != g)
-                                    pk[kk] = await_tag(&c.xpart[(size_t)k * c.nstride + i], pk[kk], tag, tag_x, Q.err);
+                                    pk[kk] = await_tag(&c.xpart[(size_t)k * c.nstride + i], pk[kk], tag, tag_x, Q.err, Q.wait_limit);
                                 xs += pk[kk] ^ ((int64_t)tag << 61);
                             }
                         }
@@ -1082,7 +1083,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         if (c.sample) {
             for (int q = tid; q < c.groups; q += NT) {
                 if (q >= c.q_lo && q < c.q_hi) continue;
-                const uint32_t word = await_tag(&c.vbuf[q], xload(&c.vbuf[q]), tag, tag_v, Q.err);
+                const uint32_t word = await_tag(&c.vbuf[q], xload(&c.vbuf[q]), tag, tag_v, Q.err, Q.wait_limit);
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (q * 4 + k < N) L.v[q * 4 + k] = (uint8_t)((word >> (8 * k)) & 1u);
@@ -1390,6 +1391,7 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     Q.err = p.d_err;
     Q.nstride = p.nstride;
     Q.G = p.split;
+    Q.wait_limit = p.wait_limit > 0 ? (uint32_t)p.wait_limit : kMailSpins;
     Q.xcd_map = p.xcd_map;
     Q.n_xcd = 8;
     // every mailbox starts with tag 0 (no sweep's tag)

@@ -46,7 +46,7 @@ class HpOpts(ct.Structure):
     _fields_ = [("chains", ct.c_int32), ("temp_of_chain", ct.POINTER(ct.c_int32)),
                 ("precision", ct.c_int32), ("alpha", ct.c_double), ("seed", ct.c_uint64),
                 ("threads", ct.c_int32), ("split", ct.c_int32), ("kernel", ct.c_int32),
-                ("graph", ct.c_int32), ("size_rbms", ct.c_void_p)]
+                ("graph", ct.c_int32), ("size_rbms", ct.c_void_p), ("split_wait_limit", ct.c_int32)]
 
 
 class HpPlanInfo(ct.Structure):
@@ -163,11 +163,13 @@ class Plan:
     n_vars: list of N_f.  W: [T][K][L], b: [T][L] canonical OR-gate RBMs.
     size_rbms: None, or the size-clustered model (Sec. 4): a dict K -> (W
     [T][K][L_K], b [T][L_K]) for K = 3 .. max(K, 3), L_K = 3 for K = 3 and
-    K + 1 otherwise; each clause then uses the RBM of its own length."""
+    K + 1 otherwise; each clause then uses the RBM of its own length.
+    split_wait_limit: reloads of an exchanged word before a split workgroup
+    gives up (0 = about a second); a tiny value forces the failure path."""
 
     def __init__(self, tables, n_vars, W, b, *, chains, temps=None, precision="f64",
                  alpha=1e-3, seed=0, threads=0, split=0, kernel="auto", graph=False,
-                 stream=None, size_rbms=None):
+                 stream=None, size_rbms=None, split_wait_limit=0):
         lib = load()
         tables = [np.asarray(t, dtype=np.int32) for t in tables]
         n_vars = [int(n) for n in n_vars]
@@ -208,7 +210,7 @@ class Plan:
             self._size_struct = sr
         opts = HpOpts(self.B, tp, PRECISION[precision], float(alpha), int(seed) & (2 ** 64 - 1),
                       int(threads), int(split), KERNEL[kernel], int(bool(graph)),
-                      ct.cast(sr, ct.c_void_p) if sr is not None else None)
+                      ct.cast(sr, ct.c_void_p) if sr is not None else None, int(split_wait_limit))
         h = ct.c_void_p()
         _check(lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts),
                            _stream_handle(stream)))

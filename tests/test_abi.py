@@ -66,7 +66,7 @@ def _plan_status(lib, tables, ns, W, b, **kw):
             sr[i] = hp.HpRbm(k, l, t, hp._ptr(Wg, ct.c_double), hp._ptr(bg, ct.c_double))
     opts = hp.HpOpts(kw.get("B", 2), tp, kw.get("prec", hp.HP_FP64), kw.get("alpha", 1e-3), 0,
                      kw.get("threads", 0), kw.get("split", 0), kw.get("kernel", 0), 0,
-                     ct.cast(sr, ct.c_void_p) if sr is not None else None)
+                     ct.cast(sr, ct.c_void_p) if sr is not None else None, kw.get("wait", 0))
     h = ct.c_void_p()
     st = lib.hp_plan(ct.byref(h), ct.byref(cnf), ct.byref(rbm), ct.byref(opts), None)
     assert not h.value            # never a partial plan
@@ -92,6 +92,7 @@ CASES = [
     ("split not a power of two", dict(split=3), hp.HP_EINVAL),
     ("split too large", dict(split=32), hp.HP_EINVAL),
     ("unknown kernel variant", dict(kernel=5), hp.HP_EINVAL),
+    ("negative split wait limit", dict(wait=-1), hp.HP_EINVAL),
     ("size RBM with the wrong L", dict(size=[(3, 4, 2, 0.1)]), hp.HP_EINVAL),
     ("size RBM with the wrong K", dict(size=[(4, 5, 2, 0.1)]), hp.HP_EINVAL),
     ("size RBM with another n_temps", dict(size=[(3, 3, 1, 0.1)]), hp.HP_EINVAL),

@@ -329,6 +329,28 @@ def test_split_two_owned_variables_per_thread(hip, prec):
     _same(ref, got)
 
 
+def test_split_wait_limit_reports_a_failed_exchange(hip):
+    """The failure path of the split exchange, forced from the host: with a
+    wait limit of one reload a workgroup gives up as soon as another's word
+    has not arrived yet; every workgroup still exits, hp_check reports the
+    void run, and a plan with the default limit is unaffected."""
+    from paper_2311_02101_amd import hp
+    w = wl.config_workload("plain_n4096_b64")
+    say("[split wait limit] n4096 64 chains, limit 1, 200 sweeps")
+    plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps, seed=w.seed, split_wait_limit=1)
+    assert plan.split > 1
+    st = plan.new_state(w.v0)
+    plan.run(st, 200)
+    with pytest.raises(hp.HpError):
+        plan.check()
+    plan.free()
+    ok = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps, seed=w.seed)
+    st = ok.new_state(w.v0)
+    ok.run(st, 20)
+    ok.check()
+    ok.free()
+
+
 def test_split_tiny_ragged_members(hip):
     """Members that own a single variable group and members with no clauses;
     a split that would leave a member without variables is refused."""
