@@ -9,6 +9,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hp_internal.hpp"
@@ -277,63 +278,54 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     const int64_t NV = cnf->var_offset[F], NC = cnf->clause_offset[F];
     if ((int64_t)K * NC >= (int64_t(1) << 32)) return fail(HP_EUNSUPPORTED, "too many clause slots");
 
-    // --- clause table: padding normalisation + packing (idx | neg << 15) ---
+    // --- per formula (independent, so formulas are packed on host threads):
+    //   clause table: padding normalisation + packing (idx | neg << 15);
+    //   per-variable occurrence lists, (c, k) ascending (formula f's lists
+    //   start at K * clause_offset[f]: every clause has K slots);
+    //   push-kernel clause records: length, padding merge, sort by length.
+    //   len = K minus the trailing run of copies of literal 0 (the padding of
+    //   Sec. 3.3); positions >= len contribute through the merged slot 0.
     std::vector<uint16_t> lits((size_t)K * NC);
     std::vector<uint32_t> deg(NV, 0);
-    for (int f = 0; f < F; ++f) {
-        const int64_t n = cnf->var_offset[f + 1] - cnf->var_offset[f];
-        for (int64_t c = cnf->clause_offset[f]; c < cnf->clause_offset[f + 1]; ++c) {
+    std::vector<uint32_t> csr_ptr(NV + F);
+    std::vector<uint32_t> occ((size_t)K * NC);
+    std::vector<uint4> rec(NC);
+    std::vector<uint32_t> orig(NC);
+    std::vector<uint32_t> push_slots(NV, 0);
+    std::vector<int32_t> negcnt(NV, 0);
+    std::vector<std::string> pack_err(F);
+    auto pack_formula = [&](int f) -> std::string {
+        const int64_t v0 = cnf->var_offset[f], n = cnf->var_offset[f + 1] - v0;
+        const int64_t c0 = cnf->clause_offset[f], c1 = cnf->clause_offset[f + 1];
+        for (int64_t c = c0; c < c1; ++c) {
             int32_t first = 0;
             for (int k = 0; k < K; ++k)
                 if (cnf->lits[(size_t)k * NC + c] != 0) {
                     first = cnf->lits[(size_t)k * NC + c];
                     break;
                 }
-            if (first == 0) return fail(HP_EINVAL, "clause " + std::to_string(c) + " has no literal");
+            if (first == 0) return "clause " + std::to_string(c) + " has no literal";
             for (int k = 0; k < K; ++k) {
                 int32_t x = cnf->lits[(size_t)k * NC + c];
                 if (x == 0) x = first;
                 const int64_t a = x < 0 ? -(int64_t)x : (int64_t)x;
-                if (a > n) return fail(HP_EINVAL, "literal " + std::to_string(x) + " exceeds N_f");
+                if (a > n) return "literal " + std::to_string(x) + " exceeds N_f";
                 lits[(size_t)k * NC + c] = (uint16_t)((a - 1) | (x < 0 ? 0x8000u : 0u));
-                deg[cnf->var_offset[f] + a - 1]++;
+                deg[v0 + a - 1]++;
             }
         }
-    }
-    // --- per-variable occurrence lists, (c, k) ascending ---
-    std::vector<uint32_t> csr_ptr(NV + F);
-    std::vector<uint32_t> occ((size_t)K * NC);
-    {
-        uint64_t pos = 0;
-        for (int f = 0; f < F; ++f) {
-            const int64_t v0 = cnf->var_offset[f], n = cnf->var_offset[f + 1] - v0;
-            for (int64_t i = 0; i < n; ++i) {
-                csr_ptr[v0 + f + i] = (uint32_t)pos;
-                pos += deg[v0 + i];
+        uint64_t pos = (uint64_t)K * (uint64_t)c0;
+        for (int64_t i = 0; i < n; ++i) {
+            csr_ptr[v0 + f + i] = (uint32_t)pos;
+            pos += deg[v0 + i];
+        }
+        csr_ptr[v0 + f + n] = (uint32_t)pos;
+        std::vector<uint32_t> fill(csr_ptr.begin() + v0 + f, csr_ptr.begin() + v0 + f + n);
+        for (int64_t c = c0; c < c1; ++c)
+            for (int k = 0; k < K; ++k) {
+                const uint16_t e = lits[(size_t)k * NC + c];
+                occ[fill[e & 0x7fff]++] = ((uint32_t)(c - c0) << 4) | ((e >> 15) << 3) | (uint32_t)k;
             }
-            csr_ptr[v0 + f + n] = (uint32_t)pos;
-        }
-        std::vector<uint32_t> fill(NV + F);
-        for (int64_t i = 0; i < NV + F; ++i) fill[i] = csr_ptr[i];
-        for (int f = 0; f < F; ++f) {
-            const int64_t v0 = cnf->var_offset[f], c0 = cnf->clause_offset[f];
-            for (int64_t c = c0; c < cnf->clause_offset[f + 1]; ++c)
-                for (int k = 0; k < K; ++k) {
-                    const uint16_t e = lits[(size_t)k * NC + c];
-                    const int64_t slot = v0 + f + (e & 0x7fff);
-                    occ[fill[slot]++] = ((uint32_t)(c - c0) << 4) | ((e >> 15) << 3) | (uint32_t)k;
-                }
-        }
-    }
-    // --- push-kernel clause records: length, padding merge, sort by length ---
-    // len = K minus the trailing run of copies of literal 0 (the padding of
-    // Sec. 3.3); positions >= len contribute through the merged slot 0.
-    std::vector<uint4> rec(NC);
-    std::vector<uint32_t> orig(NC);
-    std::vector<uint32_t> push_slots(NV, 0);
-    std::vector<int32_t> negcnt(NV, 0);
-    for (int f = 0; f < F; ++f) {
-        const int64_t c0 = cnf->clause_offset[f], c1 = cnf->clause_offset[f + 1];
         std::vector<std::pair<int, int64_t>> key;
         key.reserve(c1 - c0);
         for (int64_t c = c0; c < c1; ++c) {
@@ -342,8 +334,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
             key.push_back({len, c});
             for (int k = 0; k < len; ++k) {
                 const uint16_t e = lits[(size_t)k * NC + c];
-                push_slots[cnf->var_offset[f] + (e & 0x7fff)]++;
-                if (e >> 15) negcnt[cnf->var_offset[f] + (e & 0x7fff)]++;
+                push_slots[v0 + (e & 0x7fff)]++;
+                if (e >> 15) negcnt[v0 + (e & 0x7fff)]++;
             }
         }
         std::stable_sort(key.begin(), key.end(),
@@ -362,6 +354,32 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
                                      sl[4] | ((uint32_t)sl[5] << 16), sl[6] | ((uint32_t)sl[7] << 16));
             orig[c0 + j] = (uint32_t)(c - c0);
         }
+        return std::string();
+    };
+    {
+        // contiguous runs of formulas of about equal clause counts per thread
+        int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+        if (F < 2 || NC < (int64_t(1) << 16)) nt = 1;
+        nt = std::min(nt, F);
+        std::vector<int> first(nt + 1, F);
+        first[0] = 0;
+        for (int t = 1, f = 0; t < nt; ++t) {
+            const int64_t target = NC * t / nt;
+            while (f < F && cnf->clause_offset[f] < target) ++f;
+            first[t] = f;
+        }
+        auto run = [&](int t) {
+            for (int f = first[t]; f < first[t + 1]; ++f) pack_err[f] = pack_formula(f);
+        };
+        if (nt == 1) {
+            run(0);
+        } else {
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nt; ++t) pool.emplace_back(run, t);
+            for (std::thread &th : pool) th.join();
+        }
+        for (int f = 0; f < F; ++f)
+            if (!pack_err[f].empty()) return fail(HP_EINVAL, pack_err[f]);
     }
     // fixed-point scale: every slot contributes at most Wsum = sum |W_c| in
     // magnitude, a variable has at most max_slots slots, so |x| * 2^S stays
