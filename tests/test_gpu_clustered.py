@@ -44,7 +44,7 @@ def _teacher_forced(plan, st, f, ost, cp, temps, *, alpha, seed, prec, chain_ids
 
 
 def _trajectory(tables, ns, rbms, B, S, prec, seed, label, alpha=1e-3):
-    W7, b7 = rbms[7]
+    W7, b7 = rbms[max(tables[0].shape[0], 3)]     # the padded-model RBM the plan also takes
     temps = wl.default_temperatures(B, W7.shape[0])
     say(f"[{label}] clustered plan F={len(tables)} N={list(ns)} B={B} S={S} prec={prec} seed={seed}")
     plan = hp.Plan(tables, ns, W7, b7, chains=B, temps=temps, precision=prec, alpha=alpha, seed=seed,
@@ -97,6 +97,17 @@ def test_gaussian_rbms_and_short_clauses(hip):
     rbms = {K: (0.7 * rng.standard_normal((2, K, CL.hidden_units(K))),
                 0.7 * rng.standard_normal((2, CL.hidden_units(K)))) for K in range(3, 8)}
     _trajectory([T], [n], rbms, 4, 30, "f64", 13, "clust gaussian")
+
+
+def test_narrow_table_needs_only_the_small_groups(hip):
+    """A K = 4 table (clauses of 1..4 literals): the plan takes the K = 3 and
+    K = 4 RBMs only; FP64 trajectory against the oracle."""
+    n = 200
+    T = wl.random_formula(n, 16, k=4, lengths=[1, 2, 3, 4], probs=[0.1, 0.4, 0.3, 0.2])
+    assert T.shape[0] == 4
+    full = wl.pretrained_size_rbms()
+    rbms = {3: full[3], 4: full[4]}
+    _trajectory([T], [n], rbms, 4, 30, "f64", 16, "clust k4")
 
 
 def test_all_seven_literal_clauses_equal_the_padded_model(hip):
