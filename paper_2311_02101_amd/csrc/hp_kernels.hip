@@ -231,11 +231,10 @@ size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off) {
 // set iff word_l <= row[l] (i.e. U < p_l).  Units of the first Philox block
 // go to bits 0..3, of the second block (L > 4) to bits 4..7; bits >= L are
 // left to the caller to mask.
+template <int SH = 0>
 __device__ __forceinline__ uint32_t draw4(const uint4 &r, const uint4 &t) {
-    uint32_t n = (uint32_t)(r.w <= t.w);
-    n = n + n + (uint32_t)(r.z <= t.z);
-    n = n + n + (uint32_t)(r.y <= t.y);
-    return n + n + (uint32_t)(r.x <= t.x);
+    return (r.x <= t.x ? 1u << SH : 0u) | (r.y <= t.y ? 2u << SH : 0u) | (r.z <= t.z ? 4u << SH : 0u) |
+           (r.w <= t.w ? 8u << SH : 0u);
 }
 
 __device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t blk, const PhiloxSweep &u, Key2 key,
@@ -247,7 +246,7 @@ __device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t bl
         uint4 r[2];
         const uint32_t w[2] = {kPhaseHidden | blk, kPhaseHidden | (blk + 1u)};
         philox_sweep_multi<2>(r, w, u, key);
-        return draw4(r[0], ta) | (draw4(r[1], tb) << 4);
+        return draw4<0>(r[0], ta) | draw4<4>(r[1], tb);
     }
     return draw4(philox_sweep(kPhaseHidden | blk, u, key), ta);
 }
@@ -386,12 +385,31 @@ __device__ __forceinline__ uint32_t lit_of(const uint8_t *s_v, uint32_t e) {
     return (uint32_t)s_v[e & 0x7fffu] ^ (e >> 15);
 }
 
-// Add pol * g to the accumulator of slot e's variable.  A negated slot adds
-// ~g = -g - 1; the missing +1 of every negated slot of a variable is a
-// constant of the formula (negcnt) that seeds the accumulator.
+// Add pol * g to the accumulator of variable i; sm = 0 for a positive slot,
+// all ones for a negated one, which adds ~g = -g - 1.  The missing +1 of every
+// negated slot of a variable is a constant of the formula (negcnt) that seeds
+// the accumulator.
+__device__ __forceinline__ void push_add(int64_t *s_x, uint32_t i, uint32_t sm, int64_t g) {
+    const uint64_t u = (uint64_t)g;
+    const uint64_t gx = ((uint64_t)((uint32_t)(u >> 32) ^ sm) << 32) | (uint64_t)((uint32_t)u ^ sm);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&s_x[i]), (unsigned long long)gx);
+}
+
+// the same for a 16-bit clause slot e (variable in bits 0..14, negation in 15)
 __device__ __forceinline__ void push_add(int64_t *s_x, uint32_t e, int64_t g) {
-    const uint64_t sm = (uint64_t)(int64_t)((int32_t)(e << 16) >> 31);   // 0 or all ones
-    atomicAdd(reinterpret_cast<unsigned long long *>(&s_x[e & 0x7fffu]), (unsigned long long)g ^ sm);
+    push_add(s_x, e & 0x7fffu, (uint32_t)((int32_t)(e << 16) >> 31), g);
+}
+
+// variable and negation mask of slot k of a record (two 16-bit slots a word)
+template <int k>
+__device__ __forceinline__ uint32_t slot_var(const uint4 &r) {
+    const uint32_t w = k < 2 ? r.x : k < 4 ? r.y : k < 6 ? r.z : r.w;
+    return (k & 1) ? __builtin_amdgcn_ubfe(w, 16, 15) : (w & 0x7fffu);
+}
+template <int k>
+__device__ __forceinline__ uint32_t slot_neg(const uint4 &r) {
+    const uint32_t w = k < 2 ? r.x : k < 4 ? r.y : k < 6 ? r.z : r.w;
+    return (uint32_t)__builtin_amdgcn_sbfe((int)w, (k & 1) ? 31 : 15, 1);
 }
 
 // The gathers and the table reads go through pointers made from constant
@@ -463,6 +481,23 @@ __device__ __forceinline__ uint32_t gather_fixed(const uint8_t *v, const uint4 &
     return m;
 }
 
+// Padding positions of a clause of len literals, filled with copies of
+// literal 0: up to the table width (full = 2^K - 1) in the padded model, up to
+// K = max(len, 3) in the size-clustered one.
+template <bool kClust>
+__device__ __forceinline__ uint32_t pad_mask(uint32_t len, uint32_t full) {
+    const uint32_t top = kClust ? (1u << (len < 3u ? 3u : len)) - 1u : full;
+    return top & ~((1u << len) - 1u);
+}
+
+// literal-truth pattern of a clause of LEN literals (negation bits of slots
+// 0..LEN-1 in bits 19.. of the record's last word), padding filled
+template <int LEN, bool kClust>
+__device__ __forceinline__ uint32_t pattern_fixed(const uint8_t *v, const uint4 &r, uint32_t full) {
+    const uint32_t m = gather_fixed<LEN>(v, r) ^ (r.w >> 19);
+    return m | (pad_mask<kClust>((uint32_t)LEN, full) & (0u - (m & 1u)));
+}
+
 __device__ __forceinline__ uint32_t gather_any(const uint8_t *v, const uint4 &r, uint32_t len) {
     uint32_t m = v[r.x & 0x7fffu];
     if (len > 1) m |= (uint32_t)v[(r.x >> 16) & 0x7fffu] << 1;
@@ -476,13 +511,18 @@ __device__ __forceinline__ uint32_t gather_any(const uint8_t *v, const uint4 &r,
 
 // Scatter of a clause's contributions: g0 (the merged slot 0) to slot 0's
 // variable, gr[k] to slot k's for k = 1..len-1.
+template <int k, int LEN>
+__device__ __forceinline__ void scatter_slots(int64_t *x, const uint4 &r, const int64_t *gr) {
+    if constexpr (k < LEN) {
+        push_add(x, slot_var<k>(r), slot_neg<k>(r), gr[k]);
+        scatter_slots<k + 1, LEN>(x, r, gr);
+    }
+}
+
 template <int LEN>
 __device__ __forceinline__ void scatter_fixed(int64_t *x, const uint4 &r, int64_t g0, const int64_t *gr) {
-    const uint32_t e[7] = {r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16, r.z & 0xffffu, r.z >> 16,
-                           r.w & 0xffffu};
-    push_add(x, e[0], g0);
-#pragma unroll
-    for (int k = 1; k < LEN; ++k) push_add(x, e[k], gr[k]);
+    push_add(x, slot_var<0>(r), slot_neg<0>(r), g0);
+    scatter_slots<1, LEN>(x, r, gr);
 }
 
 __device__ __forceinline__ void scatter_any(int64_t *x, const uint4 &r, uint32_t len, int64_t g0,
@@ -532,24 +572,20 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
         const uint32_t negm = r.w >> 19;          // negation bits of slots 0..len-1
         const int lu = __builtin_amdgcn_readfirstlane((int)len);
         const int ul = __all((int)len == lu) ? lu : 0;
-        // gather the values of the clause's variables, then apply the polarities
+        // gather the values of the clause's variables, apply the polarities
+        // and fill the padding positions with literal 0's truth
         uint32_t m;
         switch (ul) {
-            case 1: m = gather_fixed<1>(L.v, r); break;
-            case 2: m = gather_fixed<2>(L.v, r); break;
-            case 3: m = gather_fixed<3>(L.v, r); break;
-            case 4: m = gather_fixed<4>(L.v, r); break;
-            case 5: m = gather_fixed<5>(L.v, r); break;
-            case 6: m = gather_fixed<6>(L.v, r); break;
-            case 7: m = gather_fixed<7>(L.v, r); break;
-            default: m = gather_any(L.v, r, len);
-        }
-        m ^= negm;
-        if (kClust) {
-            const uint32_t Kc = len < 3u ? 3u : len;
-            m |= (m & 1u) ? (((1u << Kc) - 1u) & ~((1u << len) - 1u)) : 0u;
-        } else {
-            m |= (m & 1u) ? (full & ~((1u << len) - 1u)) : 0u;   // padding copies of literal 0
+            case 1: m = pattern_fixed<1, kClust>(L.v, r, full); break;
+            case 2: m = pattern_fixed<2, kClust>(L.v, r, full); break;
+            case 3: m = pattern_fixed<3, kClust>(L.v, r, full); break;
+            case 4: m = pattern_fixed<4, kClust>(L.v, r, full); break;
+            case 5: m = pattern_fixed<5, kClust>(L.v, r, full); break;
+            case 6: m = pattern_fixed<6, kClust>(L.v, r, full); break;
+            case 7: m = pattern_fixed<7, kClust>(L.v, r, full); break;
+            default:
+                m = gather_any(L.v, r, len) ^ negm;
+                m |= pad_mask<kClust>(len, full) & (0u - (m & 1u));
         }
         cnt += (m != 0u);
         if (kSample) {
@@ -565,7 +601,7 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
                 g0 = L.gpad[(len <= 3u ? 8u * (len - 1u) : (2u << len) - 8u) + n];
                 gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
             } else {
-                n = hidden_mask(L.thr + m * kMaxL, oc * nbh, ps, key, nbh) & lmask;
+                n = hidden_mask(L.thr + m * kMaxL, oc << (nbh - 1u), ps, key, nbh) & lmask;
                 g0 = L.gpad[len * kHidMasks + n];
                 gr = L.gfx + n * kMaxL;
             }
