@@ -465,6 +465,9 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         kind[f] = kind_of(f);
         if (kind[f] < 0) {
             release(p);
+            if (fx_shift < 40 && (mixed || clust || opts->kernel == HP_KERNEL_PUSH))
+                return fail(HP_EUNSUPPORTED, "the weights are too large for the push kernels' fixed-point "
+                                             "accumulators (scale 2^" + std::to_string(fx_shift) + ", need 2^40)");
             return fail(HP_EUNSUPPORTED, "formula " + std::to_string(f) + " (N = " + std::to_string(fd[f].n) +
                                              ") does not fit the workgroup LDS limit (" + std::to_string(max_lds) +
                                              " B) with the requested kernel");

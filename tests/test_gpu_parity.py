@@ -366,6 +366,25 @@ def test_split_tiny_ragged_members(hip):
         hp.Plan(tables, [29, 5], W, b, chains=8, split=8)
 
 
+def test_weights_beyond_the_fixed_point_range(hip):
+    """Weights so large that the push accumulators' fixed-point scale would
+    drop below 2^40: the automatic choice falls back to the pull kernel (FP
+    sums); the push kernel is refused with the reason."""
+    from paper_2311_02101_amd import hp
+    n = 64
+    T = wl.random_formula(n, 17)
+    W, b = wl.gaussian_rbm(1, 7, 8, 17)
+    W = np.abs(W) * 2.0 ** 13          # positive: every hidden logit >= b = 0 (no underflow)
+    b = b * 0.0
+    say("[fixed-point range] N=64 |W| ~ 2^13")
+    plan = hp.Plan([T], [n], W, b, chains=2, temps=np.zeros(2, np.int32), seed=17)
+    assert plan.info()["fx_shift"] < 40
+    assert plan.info()["bucket_kind"][0] == 2      # pull
+    plan.free()
+    with pytest.raises(hp.HpError, match="fixed-point"):
+        hp.Plan([T], [n], W, b, chains=2, temps=np.zeros(2, np.int32), seed=17, kernel="push")
+
+
 @pytest.mark.parametrize("split,chains", [(2, 16), (4, 8), (16, 2)])
 def test_split_small_formulas_many_sweeps(hip, split, chains):
     """Small exchanges repeated over many sweeps: the exchanged lines stay in
