@@ -243,6 +243,37 @@ def test_resume_and_count_only(hip):
     assert np.array_equal(best, v0) and d.get_t() == 0 and np.all(nu == 0.25)
 
 
+def test_split_resume_and_count_only(hip):
+    """The split launch is resumable like the single one (runs of 7, 0 and 5
+    sweeps equal one of 12, the best-state decisions settled inside each
+    launch) and a zero-sweep run counts the current state."""
+    from paper_2311_02101_amd import hp
+    w = wl.config_workload("plain_n4096_b64")
+    T, n, v0 = w.tables[0], w.n_vars[0], w.v0[0]
+    say("[split resume] n4096 64 chains: run(12) vs run(7)+run(0)+run(5)")
+    p = hp.Plan([T], [n], w.W, w.b, chains=64, temps=w.temps, seed=w.seed)
+    assert p.split > 1
+    a = p.new_state([v0])
+    c = p.new_state([v0])
+    p.run(a, 12)
+    p.run(c, 7)
+    p.run(c, 0)
+    p.run(c, 5)
+    _sync()
+    p.check()
+    for x, y in zip(a.formula(0), c.formula(0)):
+        assert np.array_equal(x, y)
+    assert a.get_t() == c.get_t() == 12
+    d = p.new_state([v0])
+    p.run(d, 0)
+    _sync()
+    v, nu, s_max, best = d.formula(0)
+    op = R.plan(T, n, w.W, w.b)
+    assert np.array_equal(s_max, R.clause_count(v0, op))
+    assert np.array_equal(best, v0) and d.get_t() == 0
+    p.free()
+
+
 def test_stationary_distribution_on_gpu(hip):
     """The device sampler's long-run distribution is p(v) ~ exp(-F_f(v))."""
     from paper_2311_02101_amd import hp
