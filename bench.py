@@ -98,8 +98,8 @@ def main(argv=None):
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters), then exit")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(chains shard across GPUs with no per-sweep exchange; see the design notes)",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(chains and formulas would shard across GPUs with no per-sweep exchange)",
               file=sys.stderr, flush=True)
         return 2
 

@@ -19,14 +19,13 @@ an explicit ascending loop so its rounding order is visible:
                 visible conditional (eq. 3), variance EMA (Sec. 3.4) and
                 Bernoulli draw.
 
-Readings where the text is silent or inconsistent (each also listed in the
-design notes):
+Readings where the text is silent or inconsistent:
   * clause count: a literal is true iff (pol > 0) == v; the program's product
     "(polarity > 0) * c" would miss satisfied negated literals, whereas the
     text describes comparing thresholded signs with the values and OR-ing.
   * zero entries of T (Sec. 3.1 padding) are replaced by the clause's first
     non-zero literal (Sec. 3.3 pads by repetition with the same polarity).
-  * visible bias d = 0 (Sec. 3.1: "visible biases d are not required").
+  * visible bias d = 0 (Sec. 3.1 states that the formula-RBM needs none).
   * best assignment: replaced only on a strict improvement s > s_max.
   * randomness: U(t, b, phase, j) from Philox4x32-10 (see ``uniforms``);
     a draw is 1 iff U < p (the Bernoulli semantics of the program).
