@@ -87,8 +87,9 @@ def main(argv=None):
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "push", "pull"])
     ap.add_argument("--split", type=int, default=0, help="workgroups per chain (0 = automatic)")
-    ap.add_argument("--cpu-sweeps", type=int, default=10,
-                    help="sweeps of the oracle sample (all chains); 0 skips the CPU leg")
+    ap.add_argument("--cpu-sweeps", type=int, default=25,
+                    help="sweeps of the oracle sample (all chains; about 13 s of CPU work on the "
+                         "default workload); 0 skips the CPU leg")
     ap.add_argument("--graph", type=int, default=-1, help="hipGraph replay (default: on for batches)")
     ap.add_argument("--tune", type=int, default=-1, help="autotune first (default: on for batches)")
     ap.add_argument("--model", default="padded", choices=["padded", "clustered"],
