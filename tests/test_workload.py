@@ -80,3 +80,16 @@ def test_bench_work_model_of_the_clustered_model():
     # the padded model: every clause draws L = 8 units from two blocks
     c2, d2, _ = bench.chain_sweep_work(n, T.shape[1], 8)
     assert c2 == 2 * T.shape[1] + (n + 3) // 4 and d2 == 8 * T.shape[1] + n
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and a
+    message, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
