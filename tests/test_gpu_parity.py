@@ -274,6 +274,45 @@ def test_split_resume_and_count_only(hip):
     p.free()
 
 
+def test_sweep_counter_crossing_2_pow_32(hip):
+    """The absolute sweep counter t addresses the random numbers through its
+    low and high words: sweeps across t = 2^32 match the oracle (one
+    workgroup per chain), and the split launch matches the single one there."""
+    from paper_2311_02101_amd import hp
+    n, B, t0 = 256, 4, (1 << 32) - 3
+    T = wl.random_formula(n, 18)
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    temps = wl.default_temperatures(B, 2)
+    v0 = wl.initial_state(B, n, 18)
+    say(f"[t across 2^32] N={n} B={B} t0={t0}, 6 sweeps")
+    plan = hp.Plan([T], [n], W, b, chains=B, temps=temps, seed=18)
+    st = plan.new_state([v0])
+    st.set_t(t0)
+    plan.run(st, 6)
+    _sync()
+    assert st.get_t() == t0 + 6
+    op = R.plan(T, n, W, b)
+    ost = R.initial(v0)
+    ost.t = t0
+    R.run(ost, op, temps, 6, alpha=1e-3, seed=18)
+    compare_state(st.formula(0), (ost.v, ost.nu, ost.s_max, ost.best), "f64", "t across 2^32")
+    plan.free()
+    w = wl.config_workload("plain_n4096_b64")
+    out = []
+    for split in (1, 4):
+        say(f"[t across 2^32] n4096 64 chains split {split}")
+        p2 = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps, seed=w.seed, split=split)
+        s2 = p2.new_state(w.v0)
+        s2.set_t(t0)
+        p2.run(s2, 6)
+        _sync()
+        p2.check()
+        out.append(s2.formula(0))
+        p2.free()
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
+
+
 def test_stationary_distribution_on_gpu(hip):
     """The device sampler's long-run distribution is p(v) ~ exp(-F_f(v))."""
     from paper_2311_02101_amd import hp
