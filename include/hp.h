@@ -39,7 +39,7 @@ typedef enum {
     HP_EINVAL = -1,        /* invalid argument; nothing was allocated or enqueued */
     HP_ENOMEM = -2,        /* device allocation failed                            */
     HP_EDEVICE = -3,       /* a HIP runtime call failed                           */
-    HP_EUNSUPPORTED = -4   /* valid input outside what this build handles         */
+    HP_EUNSUPPORTED = -4   /* valid input outside what the library handles       */
 } hp_status;
 
 /* Arithmetic of the sweep.  HP_FP64 and HP_FP32 take the hidden draws from
@@ -166,7 +166,10 @@ typedef struct hp_plan_s *hp_plan_t;
  * 1..8 or rbm->k != cnf->k, N_f < 1 or C_f < 1, a literal with |lit| > N_f,
  * an all-zero clause, non-finite weights, alpha outside [0,1], chains < 1, a
  * temperature index outside [0, n_temps).  HP_EUNSUPPORTED: N_f > 32768, or
- * a formula whose working set exceeds the workgroup's LDS. */
+ * a formula whose working set exceeds the workgroup's LDS (160 KB on gfx950:
+ * the push kernels take 9 bytes per variable plus their tables, which covers
+ * N_f up to about 17 700; beyond that the pull kernel needs about
+ * 20 KB + N_f + C_f bytes). */
 hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
                   const hp_opts *opts, void *stream);
 

@@ -195,7 +195,7 @@ const char *hp_status_string(hp_status s) {
         case HP_EINVAL: return "HP_EINVAL: invalid argument";
         case HP_ENOMEM: return "HP_ENOMEM: device allocation failed";
         case HP_EDEVICE: return "HP_EDEVICE: HIP runtime error";
-        case HP_EUNSUPPORTED: return "HP_EUNSUPPORTED: outside what this build handles";
+        case HP_EUNSUPPORTED: return "HP_EUNSUPPORTED: outside what the library handles";
     }
     return "unknown hp_status";
 }

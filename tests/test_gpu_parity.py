@@ -313,6 +313,24 @@ def test_sweep_counter_crossing_2_pow_32(hip):
         assert np.array_equal(x, y)
 
 
+def test_largest_formulas(hip):
+    """A formula too large for the push kernels' LDS (N = 19 000, C = 114 000)
+    runs on the pull kernel and matches the oracle; one whose pull working
+    set no longer fits either (N = 21 000) is refused with HP_EUNSUPPORTED."""
+    from paper_2311_02101_amd import hp
+    n, B = 19000, 2
+    T = wl.random_formula(n, 19)
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    say(f"[largest] N={n} C={T.shape[1]} B={B}, 3 sweeps")
+    _trajectory(hip, [T], [n], W, b, B, 3, "f64", 19, label="largest N")
+    plan = hp.Plan([T], [n], W, b, chains=B, seed=19)
+    assert plan.info()["bucket_kind"] == [2]
+    plan.free()
+    big = 21000
+    with pytest.raises(hp.HpError, match="LDS"):
+        hp.Plan([wl.random_formula(big, 19)], [big], W, b, chains=B, seed=19)
+
+
 def test_stationary_distribution_on_gpu(hip):
     """The device sampler's long-run distribution is p(v) ~ exp(-F_f(v))."""
     from paper_2311_02101_amd import hp
