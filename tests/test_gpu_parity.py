@@ -194,6 +194,18 @@ def test_tiny_and_ragged_formulas(hip, kernel):
     _trajectory(hip, tables, ns, W, b, 5, 30, "f64", 4, kernel=kernel, label="tiny K=3 L=3")
 
 
+@pytest.mark.parametrize("kernel", ["push", "pull"])
+@pytest.mark.parametrize("k,l", [(1, 2), (2, 3)])
+def test_narrow_tables(hip, kernel, k, l):
+    """Tables of width K = 1 (unit clauses) and K = 2 with their own RBMs."""
+    n = 150
+    lengths = list(range(1, k + 1))
+    T = wl.random_formula(n, 20 + k, k=k, lengths=lengths, probs=[1.0 / k] * k)
+    assert T.shape[0] == k
+    W, b = wl.gaussian_rbm(2, k, l, 20 + k)
+    _trajectory(hip, [T], [n], W, b, 6, 40, "f64", 20 + k, kernel=kernel, label=f"K={k} L={l}")
+
+
 def test_zero_padded_literals_are_normalised(hip):
     n = 40
     T = wl.random_formula(n, 13, ratio=3)
