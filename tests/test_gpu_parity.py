@@ -206,6 +206,17 @@ def test_narrow_tables(hip, kernel, k, l):
     _trajectory(hip, [T], [n], W, b, 6, 40, "f64", 20 + k, kernel=kernel, label=f"K={k} L={l}")
 
 
+@pytest.mark.parametrize("k,l", [(7, 4), (7, 5), (5, 8), (4, 1)])
+def test_hidden_unit_counts(hip, k, l):
+    """Hidden-unit counts other than K + 1: one Philox block (L <= 4) or two
+    with unused words (4 < L < 8), a single hidden unit."""
+    n = 300
+    lengths = list(range(1, k + 1))
+    T = wl.random_formula(n, 30 + l, k=k, lengths=lengths, probs=[1.0 / k] * k)
+    W, b = wl.gaussian_rbm(2, k, l, 30 + l)
+    _trajectory(hip, [T], [n], W, b, 5, 30, "f64", 30 + l, label=f"K={k} L={l}")
+
+
 def test_zero_padded_literals_are_normalised(hip):
     n = 40
     T = wl.random_formula(n, 13, ratio=3)
