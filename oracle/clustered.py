@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import rbmsat as _rbmsat
 from .rbmsat import (HIDDEN, State, contributions, hidden_logits, literal_truth, normalize_table, plan,
                      scatter_add, sigmoid, uniforms, visible_uniforms)
 
@@ -108,7 +109,7 @@ def sweep(st: State, cp: ClusteredPlan, temps, *, alpha: float, seed: int, formu
         hid_margin = min([hid_margin] + [float(np.abs(u - p).min()) for u, p in zip(us, ph)])
         x[sel] = visible_logits(hs, cp, tau)
     rho = sigmoid(x)
-    st.nu = (1 - alpha) * st.nu + alpha * rho * (1 - rho)
+    st.nu = _rbmsat.variance_ema(st.nu, rho, alpha)
     u_v = visible_uniforms(seed, formula_id, t, chain_ids, pf.n_vars)
     st.v = (u_v < rho).astype(np.uint8)
     st.t = t + 1

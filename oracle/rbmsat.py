@@ -297,13 +297,22 @@ def sweep(st: State, p: Plan, temps, *, alpha: float, seed: int, formula_id: int
             rec["p_h"][sel], rec["u_h"][sel], rec["h"][sel] = ph, u_h[sel], h
     # visible conditional, variance EMA, draw
     rho = sigmoid(x)
-    st.nu = (1 - alpha) * st.nu + alpha * rho * (1 - rho)
+    st.nu = variance_ema(st.nu, rho, alpha)
     u_v = visible_uniforms(seed, formula_id, t, chain_ids, p.n_vars)
     st.v = (u_v < rho).astype(np.uint8)
     st.t = t + 1
     if record:
         rec.update(x=x, rho=rho, u_v=u_v)
     return rec
+
+
+def variance_ema(nu, rho, alpha: float):
+    """Moving average of the visible units' conditional variance (Sec. 3.4,
+    the priority of prioritized unit propagation): the variance of the
+    Bernoulli(rho) draw of a unit is rho (1 - rho), and every sweep moves nu
+    a fraction alpha towards it, nu <- (1 - alpha) nu + alpha rho (1 - rho).
+    The appendix program starts nu at 0.25 (the variance at rho = 1/2)."""
+    return (1 - alpha) * nu + alpha * rho * (1 - rho)
 
 
 def count_and_track(st: State, p: Plan):
