@@ -209,9 +209,12 @@ typedef struct {
 hp_status hp_plan_query(hp_plan_t plan, hp_plan_info *out);
 
 /* Wait for the plan's device work and report device-side failures: returns
- * HP_EDEVICE if a workgroup of a split launch (several workgroups per chain,
- * hp_opts.split) gave up waiting for the data of the others, in which case
- * the state written by the affected runs is void; HP_OK otherwise. */
+ * HP_EDEVICE if, since the plan was built or hp_check last returned, a
+ * workgroup of a split launch (several workgroups per chain, hp_opts.split)
+ * gave up waiting for the data of the others, in which case the state
+ * written by those runs is void; HP_OK otherwise.  The failure flag is
+ * sticky until this call reports it (later runs of the plan give up at once
+ * while it is raised) and is cleared by the call. */
 hp_status hp_check(hp_plan_t plan);
 
 /* Release a plan's device memory (synchronises the device first).  NULL is

@@ -539,8 +539,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         Bucket &bk = p->buckets[0];
         const int saved = bk.threads;
         if (opts->threads == 0) bk.threads = kMaxThreads;
-        const int occ = split_occupancy(*p);
-        const int64_t capacity = (int64_t)p->cus * occ;
+        // resident workgroups of the variant a split of G members launches
+        auto capacity = [&](int G) { return (int64_t)p->cus * split_occupancy(*p, G); };
         const int n_items = bk.count;
         // every member owns at least one group of 4 variables
         int min_groups = INT32_MAX;
@@ -552,17 +552,17 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
                 return fail(HP_EUNSUPPORTED, "split " + std::to_string(G) + " needs more than " +
                                                  std::to_string(4 * (G - 1)) + " variables in every formula");
             }
-            if ((int64_t)n_items * G > capacity) {
+            if ((int64_t)n_items * G > capacity(G)) {
                 release(p);
                 return fail(HP_EUNSUPPORTED, "split " + std::to_string(G) + ": " +
                                                  std::to_string((int64_t)n_items * G) +
                                                  " workgroups cannot all be resident (capacity " +
-                                                 std::to_string(capacity) + ")");
+                                                 std::to_string(capacity(G)) + ")");
             }
         } else {
             // largest power of two that keeps every workgroup resident and
             // leaves each member at least 1024 clauses
-            while (G * 2 <= kMaxSplit && G * 2 <= min_groups && (int64_t)n_items * G * 2 <= capacity &&
+            while (G * 2 <= kMaxSplit && G * 2 <= min_groups && (int64_t)n_items * G * 2 <= capacity(G * 2) &&
                    bk.max_c / (G * 2) >= 1024)
                 G *= 2;
         }
@@ -826,9 +826,13 @@ hp_status hp_check(hp_plan_t plan) {
     hipError_t e = hipDeviceSynchronize();
     int32_t flag = 0;
     if (e == hipSuccess) e = hipMemcpy(&flag, p->d_err, sizeof(flag), hipMemcpyDeviceToHost);
+    // the flag stays raised from the failing run until it is reported here;
+    // clearing it lets later runs wait for their data again
+    if (e == hipSuccess && flag) e = launch_zero(reinterpret_cast<uint32_t *>(p->d_err), 1, nullptr);
+    if (e == hipSuccess && flag) e = hipDeviceSynchronize();
     (void)hipSetDevice(cur);
     if (e != hipSuccess) return hip_fail(e, "hp_check");
-    if (flag) return fail(HP_EDEVICE, "a split workgroup timed out waiting for the others; results of the affected runs are void");
+    if (flag) return fail(HP_EDEVICE, "a split workgroup timed out waiting for the others; results of the runs since the last check are void");
     return HP_OK;
 }
 

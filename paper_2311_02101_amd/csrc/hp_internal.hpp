@@ -241,8 +241,12 @@ int bucket_occupancy(const Plan &p, const Bucket &b);
 
 hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t s);
 
-// resident workgroups per CU of the split kernel for this plan's launch shape
-int split_occupancy(const Plan &p);
+// owned variables per thread of a split member (1 or 2 in registers, else
+// 0) for the largest formula, G members and the given workgroup size
+int split_vpt(int max_n, int G, int threads);
+// resident workgroups per CU of the split kernel variant that a launch with G
+// members per chain runs (the VPT of split_vpt) at this plan's shape
+int split_occupancy(const Plan &p, int G);
 
 // LDS bytes of the two kernel variants for the largest formula
 size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);

@@ -512,28 +512,37 @@ __device__ __forceinline__ uint32_t gather_any(const uint8_t *v, const uint4 &r,
 // Scatter of a clause's contributions: g0 (the merged slot 0) to slot 0's
 // variable, gr[k] to slot k's for k = 1..len-1.
 template <int k, int LEN>
-__device__ __forceinline__ void scatter_slots(int64_t *x, const uint4 &r, const int64_t *gr) {
+__device__ __forceinline__ void scatter_slots(int64_t *x, const uint4 &r, const int64_t (&g)[8]) {
     if constexpr (k < LEN) {
-        push_add(x, slot_var<k>(r), slot_neg<k>(r), gr[k]);
-        scatter_slots<k + 1, LEN>(x, r, gr);
+        push_add(x, slot_var<k>(r), slot_neg<k>(r), g[k]);
+        scatter_slots<k + 1, LEN>(x, r, g);
     }
 }
 
+// All of the clause's table entries are read before the first accumulator
+// update: the compiler cannot tell that the atomics never touch the tables,
+// so reads placed after an atomic would each wait for it.
 template <int LEN>
 __device__ __forceinline__ void scatter_fixed(int64_t *x, const uint4 &r, int64_t g0, const int64_t *gr) {
-    push_add(x, slot_var<0>(r), slot_neg<0>(r), g0);
-    scatter_slots<1, LEN>(x, r, gr);
+    int64_t g[8];
+    g[0] = g0;
+#pragma unroll
+    for (int k = 1; k < LEN; ++k) g[k] = gr[k];
+    scatter_slots<0, LEN>(x, r, g);
 }
 
 __device__ __forceinline__ void scatter_any(int64_t *x, const uint4 &r, uint32_t len, int64_t g0,
                                             const int64_t *gr) {
+    int64_t g[7];
+#pragma unroll
+    for (int k = 1; k < 7; ++k) g[k] = gr[k];      // rows hold 8 entries: in bounds for any len
     push_add(x, r.x & 0xffffu, g0);
-    if (len > 1) push_add(x, r.x >> 16, gr[1]);
-    if (len > 2) push_add(x, r.y & 0xffffu, gr[2]);
-    if (len > 3) push_add(x, r.y >> 16, gr[3]);
-    if (len > 4) push_add(x, r.z & 0xffffu, gr[4]);
-    if (len > 5) push_add(x, r.z >> 16, gr[5]);
-    if (len > 6) push_add(x, r.w & 0xffffu, gr[6]);
+    if (len > 1) push_add(x, r.x >> 16, g[1]);
+    if (len > 2) push_add(x, r.y & 0xffffu, g[2]);
+    if (len > 3) push_add(x, r.y >> 16, g[3]);
+    if (len > 4) push_add(x, r.z & 0xffffu, g[4]);
+    if (len > 5) push_add(x, r.z >> 16, g[5]);
+    if (len > 6) push_add(x, r.w & 0xffffu, g[6]);
 }
 
 // Clause phase over the clause records c = c_first + c_step * j, c < c_end,
@@ -1323,10 +1332,18 @@ int bucket_occupancy(const Plan &p, const Bucket &b) {
     return nb;
 }
 
-int split_occupancy(const Plan &p) {
+int split_vpt(int max_n, int G, int threads) {
+    const int groups = (max_n + 3) / 4;
+    const int owned = 4 * ((groups + G - 1) / G);   // variables per member
+    return owned <= threads ? 1 : owned <= 2 * threads ? 2 : 0;
+}
+
+int split_occupancy(const Plan &p, int G) {
     int nb = 0;
-    const void *kern = p.precision == HP_FP64 ? split_kernel_ptr<double>(p.clust, 1) : split_kernel_ptr<float>(p.clust, 1);
     const Bucket &b = p.buckets[0];
+    const int vpt = split_vpt(b.max_n, G, b.threads);
+    const void *kern = p.precision == HP_FP64 ? split_kernel_ptr<double>(p.clust, vpt)
+                                              : split_kernel_ptr<float>(p.clust, vpt);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, b.threads, b.lds) != hipSuccess) return 0;
     return nb;
 }
@@ -1435,9 +1452,7 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_vbuf), (int64_t)b.count * p.nstride / 4, s);
     if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_cnt), (int64_t)b.count * 2 * kMaxSplit, s);
     if (e != hipSuccess) return e;
-    const int groups = (b.max_n + 3) / 4;
-    const int owned = 4 * ((groups + p.split - 1) / p.split);   // variables per member
-    return launch_split_one<Real>(p, P, Q, owned <= b.threads ? 1 : owned <= 2 * b.threads ? 2 : 0, s);
+    return launch_split_one<Real>(p, P, Q, split_vpt(b.max_n, p.split, b.threads), s);
 }
 
 // All launches of one run: a split launch, one bucket on the caller's

@@ -311,31 +311,42 @@ class State:
                        self.best.data_ptr(), self.t.data_ptr(), p.total_vars, p.F, p.B,
                        self.nu.element_size())
 
-    def formula(self, f):
-        """Host copies (v, nu, s_max, best) of formula f as [B][N_f] arrays."""
+    def formula(self, f, chains=None):
+        """Host copies (v, nu, s_max, best) of formula f as [B][N_f] arrays
+        (only the listed chains' rows if ``chains`` is given)."""
         p = self.plan
         a, n = int(p.var_offset[f]) * p.B, p.n_vars[f]
         sl = slice(a, a + n * p.B)
-        return (self.v[sl].cpu().numpy().reshape(p.B, n),
-                self.nu[sl].cpu().numpy().reshape(p.B, n),
-                self.s_max[f * p.B:(f + 1) * p.B].cpu().numpy().astype(np.int64),
-                self.best[sl].cpu().numpy().reshape(p.B, n))
+        out = (self.v[sl].cpu().numpy().reshape(p.B, n),
+               self.nu[sl].cpu().numpy().reshape(p.B, n),
+               self.s_max[f * p.B:(f + 1) * p.B].cpu().numpy().astype(np.int64),
+               self.best[sl].cpu().numpy().reshape(p.B, n))
+        if chains is not None:
+            rows = np.asarray(chains, dtype=np.int64)
+            out = tuple(x[rows] for x in out)
+        return out
 
-    def set_formula(self, f, v=None, nu=None, s_max=None, best=None):
+    def set_formula(self, f, v=None, nu=None, s_max=None, best=None, chains=None):
+        """Overwrite the state of formula f ([B][N_f] arrays), or of the listed
+        chains only ([len(chains)][N_f])."""
         import torch
         p = self.plan
         a, n = int(p.var_offset[f]) * p.B, p.n_vars[f]
         sl = slice(a, a + n * p.B)
         dev = self.v.device
+        rows = slice(None) if chains is None else torch.as_tensor(np.asarray(chains, dtype=np.int64), device=dev)
+
+        def put(dst, src, dtype):
+            dst.view(p.B, -1)[rows] = torch.from_numpy(np.ascontiguousarray(src).reshape(-1, dst.numel() // p.B)).to(
+                dev, dtype)
         if v is not None:
-            self.v[sl] = torch.from_numpy(np.ascontiguousarray(v, dtype=np.uint8).reshape(-1)).to(dev)
+            put(self.v[sl], np.asarray(v, dtype=np.uint8), torch.uint8)
         if nu is not None:
-            self.nu[sl] = torch.from_numpy(np.ascontiguousarray(nu).reshape(-1)).to(dev, self.nu.dtype)
+            put(self.nu[sl], np.asarray(nu), self.nu.dtype)
         if s_max is not None:
-            self.s_max[f * p.B:(f + 1) * p.B] = torch.from_numpy(
-                np.asarray(s_max, dtype=np.int32)).to(dev)
+            put(self.s_max[f * p.B:(f + 1) * p.B], np.asarray(s_max, dtype=np.int32), torch.int32)
         if best is not None:
-            self.best[sl] = torch.from_numpy(np.ascontiguousarray(best, dtype=np.uint8).reshape(-1)).to(dev)
+            put(self.best[sl], np.asarray(best, dtype=np.uint8), torch.uint8)
 
     def set_t(self, t):
         self.t.fill_(int(t))

@@ -212,6 +212,7 @@ def make_dataset(n_formulas, n_vars=2048, seed=4, chains=32, sweeps=500, batch=2
         xs.append(features(plan))
         ys.append(chain_mean(plan, st.best))
         torch.cuda.synchronize()
+        plan.check()              # labels of a void (failed split exchange) run are refused
         plan.free()
         if log:
             log(f"labelled {lo + k}/{n_formulas} formulas ({time.time() - t_start:.1f} s)")
@@ -263,6 +264,7 @@ def evaluate(net, n_formulas, n_vars=2048, seed=4, chains=64, sweeps=(20, 100, 5
         done = s
         plan.run(st, 0)
         torch.cuda.synchronize()
+        plan.check()
         smax = st.s_max.cpu().numpy().reshape(n_formulas, chains)
         mlp_best = smax[:, :half].max(axis=1)
         uni_best = smax[:, half:].max(axis=1)

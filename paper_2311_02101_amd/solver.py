@@ -170,6 +170,7 @@ def main(argv=None):
         stats = solve(plan, tables, st, sweeps, upp, args.upw, args.threads, temper_every=temper)
         plan.run(st, 0)                     # count the final states too
         torch.cuda.synchronize()
+        plan.check()                        # a failed split exchange voids the run
         wall = time.perf_counter() - t0
         best = [int(st.formula(f)[2].max()) for f in range(len(tables))]
         if temper:

@@ -7,7 +7,7 @@ import pytest
 
 from oracle import rbmsat as R
 from paper_2311_02101_amd import workload as wl
-from tests.parity import compare_state, say, teacher_forced_sweep
+from tests.parity import compare_state, f64_bounds, say, teacher_forced_sweep
 
 pytestmark = pytest.mark.gpu
 
@@ -18,19 +18,23 @@ def _sync():
 
 
 def _trajectory(hip, tables, ns, W, b, B, S, prec, seed, alpha=1e-3, temps=None,
-                chains=None, formulas=None, threads=0, kernel="auto", label=""):
+                chains=None, formulas=None, threads=0, kernel="auto", label="", check_plan=None):
     """Run S sweeps on the GPU and on the oracle (for the listed formulas and
     chains); compare final states exactly.  On a mismatch, replay with
-    teacher forcing and require every difference to be a flagged tie."""
+    teacher forcing and require every difference to be a flagged tie.
+    check_plan(info) may assert on the launch the plan chose."""
     from paper_2311_02101_amd import hp
     temps = wl.default_temperatures(B, W.shape[0]) if temps is None else np.asarray(temps)
     say(f"[{label}] plan F={len(tables)} N={list(ns)[:6]} B={B} S={S} prec={prec} seed={seed} "
         f"kernel={kernel}")
     plan = hp.Plan(tables, ns, W, b, chains=B, temps=temps, precision=prec, alpha=alpha,
                    seed=seed, threads=threads, kernel=kernel)
+    if check_plan is not None:
+        check_plan(plan.info())
+    tie, nu_rtol = f64_bounds(plan, tables) if prec in ("f64", "mixed") else (None, None)
     v0s = [wl.initial_state(B, n, seed, tag=f) for f, n in enumerate(ns)]
     st = plan.new_state(v0s)
-    say(f"[{label}] gpu run")
+    say(f"[{label}] gpu run (tie bound {tie}, nu rtol {nu_rtol})")
     plan.run(st, S)
     _sync()
     assert st.get_t() == S
@@ -43,18 +47,18 @@ def _trajectory(hip, tables, ns, W, b, B, S, prec, seed, alpha=1e-3, temps=None,
         gv, gnu, gs, gbest = st.formula(f)
         got = (gv[chains], gnu[chains], gs[chains], gbest[chains])
         try:
-            compare_state(got, (ost.v, ost.nu, ost.s_max, ost.best), prec, f"{label} f={f}")
+            compare_state(got, (ost.v, ost.nu, ost.s_max, ost.best), prec, f"{label} f={f}", nu_rtol=nu_rtol)
         except AssertionError as err:
             say(f"[{label}] f={f}: trajectory mismatch ({err}); replaying with teacher forcing")
-            # replay the whole run sweep by sweep on a fresh plan of this formula
-            sub = hp.Plan([tables[f]], [ns[f]], W, b, chains=B, temps=temps, precision=prec,
-                          alpha=alpha, seed=seed, threads=threads, kernel=kernel)
-            sst = sub.new_state([v0s[f]])
-            o2 = R.initial(v0s[f])
+            # replay the whole run sweep by sweep in the same plan (same formula
+            # id, hence the same random stream) on a second state, so every
+            # differing bit of every sweep must be a flagged tie
+            sst = plan.new_state(v0s)
+            o2 = R.initial(v0s[f][chains])
             ties = 0
             for _ in range(S):
-                ties += teacher_forced_sweep(sub, sst, 0, o2, op, temps, alpha=alpha, seed=seed,
-                                             prec=prec)
+                ties += teacher_forced_sweep(plan, sst, f, o2, op, temps, alpha=alpha, seed=seed,
+                                             prec=prec, chain_ids=chains, tie=tie, nu_rtol=nu_rtol)
             say(f"[{label}] f={f}: {ties} flagged ties over {S} sweeps")
             assert ties > 0, "trajectory mismatch without any tie"
     plan.free()
@@ -116,12 +120,16 @@ def test_push_and_pull_kernels_agree(hip):
             assert np.array_equal(a, c)
 
 
+@pytest.mark.timeout(600)
 def test_plain_n4096_b64_fp32_teacher_forced_all_chains(hip):
+    """The FP32 form of the 4096-variable, 64-chain workload in its own
+    (split) launch: all 64 chains, 10 teacher-forced sweeps."""
     from paper_2311_02101_amd import hp
     w = wl.config_workload("plain_n4096_b64", precision="f32")
-    say("[n4096 fp32] teacher forced, 64 chains x 2 sweeps")
+    say("[n4096 fp32] teacher forced, 64 chains x 10 sweeps")
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps, precision="f32",
                    seed=w.seed)
+    assert plan.split > 1
     st = plan.new_state(w.v0)
     plan.run(st, 25)             # move away from the initial state first
     _sync()
@@ -129,10 +137,11 @@ def test_plain_n4096_b64_fp32_teacher_forced_all_chains(hip):
     op = R.plan(w.tables[0], 4096, w.W, w.b)
     ost = R.State(v, nu.astype(np.float64), s_max, best, 25)
     ties = 0
-    for _ in range(2):
+    for i in range(10):
         ties += teacher_forced_sweep(plan, st, 0, ost, op, w.temps, alpha=1e-3, seed=w.seed,
                                      prec="f32")
-    say(f"[n4096 fp32] flagged ties: {ties}")
+        say(f"[n4096 fp32] sweep {i + 1}/10, flagged ties so far: {ties}")
+    plan.free()
 
 
 # --------------------------------------------------------------------------
@@ -318,7 +327,8 @@ def test_sweep_counter_crossing_2_pow_32(hip):
     ost = R.initial(v0)
     ost.t = t0
     R.run(ost, op, temps, 6, alpha=1e-3, seed=18)
-    compare_state(st.formula(0), (ost.v, ost.nu, ost.s_max, ost.best), "f64", "t across 2^32")
+    compare_state(st.formula(0), (ost.v, ost.nu, ost.s_max, ost.best), "f64", "t across 2^32",
+                  nu_rtol=f64_bounds(plan, [T])[1])
     plan.free()
     w = wl.config_workload("plain_n4096_b64")
     out = []
@@ -454,6 +464,7 @@ def test_split_wait_limit_reports_a_failed_exchange(hip):
     plan.run(st, 200)
     with pytest.raises(hp.HpError):
         plan.check()
+    plan.check()                  # reported once: the flag is cleared
     plan.free()
     ok = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=64, temps=w.temps, seed=w.seed)
     st = ok.new_state(w.v0)
