@@ -183,6 +183,25 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
  * exchange buffers): issue them on one stream or order them with events. */
 hp_status hp_run(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sweeps as hp_run, bit for bit, but the run's scratch -- the persistent
+ * launches' work counters and, for a split plan, the exchange mailboxes
+ * between the workgroups of a chain -- comes from a static device array of
+ * the library (16 MiB, held on every device the library has planned on until
+ * the process ends) instead of the plan's buffers.  The call allocates
+ * nothing: no hipMalloc, no graph instantiation (a plan built with graph = 1
+ * launches directly here).  The state, the plan's tables and the plan's
+ * time-out flag (hp_check) are used as in hp_run.  HP_EUNSUPPORTED if the
+ * run needs more than 16 MiB of scratch (4 KiB of work counters plus, for a
+ * split plan, about items * (8 G + 1) * N_max bytes of mailboxes); the
+ * other errors are hp_run's.  Every call on one device shares that device's
+ * array, which keeps the last call's contents (each call clears what must
+ * start at zero): calls that overlap in time on one device -- on different
+ * streams, or concurrent with another plan's hp_run_noalloc -- race and
+ * their results are undefined; order them on one stream. */
+hp_status hp_run_noalloc(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
+
 /* Autotuner: for every launch of the plan, time each candidate workgroup
  * size (64..1024) on `n_sweeps` sweeps of the given state and keep the
  * fastest.  The trial runs overwrite the state's v, nu, s_max and best

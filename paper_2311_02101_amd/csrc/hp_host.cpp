@@ -681,6 +681,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         HP_TRY(hipMalloc((void **)&p->d_cnt, items * 2 * kMaxSplit * sizeof(int32_t)), "alloc counts");
     }
     HP_TRY(launch_tables(*p, s), "table kernel");
+    // set-up of hp_run_noalloc: this device's address of the static scratch
+    HP_TRY(static_scratch_init(p->device), "hipGetSymbolAddress(scratch)");
     // host staging vectors go out of scope below: wait for the copies
     HP_TRY(hipStreamSynchronize(s), "plan upload");
     int32_t tabflag = 0;
@@ -694,9 +696,8 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     return HP_OK;
 }
 
-hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *stream) {
-    g_last_error.clear();
-    Plan *p = reinterpret_cast<Plan *>(plan);
+// the checks hp_run and hp_run_noalloc share
+static hp_status check_run(const Plan *p, const hp_state *st, int64_t n_sweeps) {
     if (!p || !st) return fail(HP_EINVAL, "null argument");
     if (n_sweeps < 0) return fail(HP_EINVAL, "n_sweeps must be >= 0");
     if (!st->v || !st->nu || !st->s_max || !st->best || !st->t) return fail(HP_EINVAL, "null state buffer");
@@ -708,6 +709,15 @@ hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *str
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != p->device) return fail(HP_EINVAL, "plan was built on another device");
+    return HP_OK;
+}
+
+hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    const hp_status chk = check_run(p, st, n_sweeps);
+    if (chk != HP_OK) return chk;
+    hipError_t e = hipSuccess;
     if (!p->use_graph) {
         e = launch_sweep(*p, *st, n_sweeps, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
@@ -740,6 +750,23 @@ hp_status hp_run(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *str
     }
     e = hipGraphLaunch(ge->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return HP_OK;
+}
+
+hp_status hp_run_noalloc(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *stream) {
+    g_last_error.clear();
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    const hp_status chk = check_run(p, st, n_sweeps);
+    if (chk != HP_OK) return chk;
+    const size_t need = run_scratch_bytes(*p);
+    if (need > kScratchBytes)
+        return fail(HP_EUNSUPPORTED, "this plan's run needs " + std::to_string(need) +
+                                         " bytes of scratch; hp_run_noalloc holds at most " +
+                                         std::to_string(kScratchBytes) + " (use hp_run)");
+    void *base = static_scratch(p->device);     // resolved by hp_plan on this device
+    if (!base) return fail(HP_EDEVICE, "static scratch address not resolved on this device");
+    hipError_t e = launch_sweep(*p, *st, n_sweeps, (hipStream_t)stream, scratch_buffers(*p, base));
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
     return HP_OK;
 }
 

@@ -229,9 +229,31 @@ struct Plan {
     int32_t *d_err = nullptr;
 };
 
+// Device buffers of one run beyond its inputs and outputs: the persistent
+// launches' work counters and the split launch's exchange mailboxes.  hp_run
+// uses the plan's own; hp_run_noalloc carves them out of the library's static
+// scratch array (kScratchBytes per device).
+struct RunBuffers {
+    uint32_t *queue;             // [kMaxBuckets][32] work counters (one 128-byte line each)
+    int64_t *xpart;              // split: [items][G][nstride] partial logits
+    uint8_t *vbuf;               // split: [items][nstride] packed new values
+    int32_t *cnt;                // split: [items][2][kMaxSplit] partial counts
+};
+constexpr size_t kScratchBytes = size_t(16) << 20;
+RunBuffers plan_buffers(const Plan &p);
+// bytes of static scratch a run of this plan needs, and its layout there
+size_t run_scratch_bytes(const Plan &p);
+RunBuffers scratch_buffers(const Plan &p, void *base);
+// Resolve this device's address of the static scratch array (once per
+// device, with the device current); static_scratch returns it afterwards
+// (nullptr if it was never resolved on that device).
+hipError_t static_scratch_init(int device);
+void *static_scratch(int device);
+
 // kernels / launchers (hp_kernels.hip)
 hipError_t launch_tables(const Plan &p, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s);
+hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb);
 // one bucket alone (no fork/join, no counter advance): used by the tuner
 hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s);
 // raise the dynamic-LDS limit of every sweep kernel to `bytes` (once per plan)

@@ -37,6 +37,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 namespace hp {
@@ -1395,8 +1396,67 @@ SweepParams<Real> sweep_params(const Plan &p, const hp_state &st, int64_t n_swee
     return P;
 }
 
+// --------------------------------------------------------------------------
+// Run buffers: the plan's own, or the static scratch of hp_run_noalloc
+// --------------------------------------------------------------------------
+// The scratch array lives in this code object; on the host its name is a
+// stand-in, so kernels receive the device address that hipGetSymbolAddress
+// returns for the current device (each device has its own copy).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices] = {};
+
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+    return hipSuccess;
+}
+
+void *static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_addr[device];
+}
+
+RunBuffers plan_buffers(const Plan &p) { return RunBuffers{p.d_queue, p.d_xpart, p.d_vbuf, p.d_cnt}; }
+
+static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// layout: work counters | xpart | vbuf | counts, each 256-byte aligned
+static void scratch_layout(const Plan &p, size_t off[4], size_t *total) {
+    const size_t items = p.split > 1 ? (size_t)p.buckets[0].count : 0;
+    off[0] = 0;
+    off[1] = align256(off[0] + (size_t)kMaxBuckets * 32 * sizeof(uint32_t));
+    off[2] = align256(off[1] + items * p.split * p.nstride * sizeof(int64_t));
+    off[3] = align256(off[2] + items * p.nstride);
+    *total = align256(off[3] + items * 2 * kMaxSplit * sizeof(int32_t));
+}
+
+size_t run_scratch_bytes(const Plan &p) {
+    size_t off[4], total = 0;
+    scratch_layout(p, off, &total);
+    return total;
+}
+
+RunBuffers scratch_buffers(const Plan &p, void *base) {
+    size_t off[4], total = 0;
+    scratch_layout(p, off, &total);
+    unsigned char *b = static_cast<unsigned char *>(base);
+    const bool split = p.split > 1;
+    return RunBuffers{reinterpret_cast<uint32_t *>(b + off[0]), split ? reinterpret_cast<int64_t *>(b + off[1]) : nullptr,
+                      split ? b + off[2] : nullptr, split ? reinterpret_cast<int32_t *>(b + off[3]) : nullptr};
+}
+
 template <typename Real>
-hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s,
+                           uint32_t *queues) {
     if (b.count == 0) return hipSuccess;
     SweepParams<Real> P = sweep_params<Real>(p, st, n_sweeps);
     P.work = p.d_work + b.first;
@@ -1413,7 +1473,7 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
     int grid = b.count;
     if (b.grid > 0) {
         // the bucket's work counter sits on its own 128-byte line
-        queue = p.d_queue + 32 * (size_t)(&b - p.buckets.data());
+        queue = queues + 32 * (size_t)(&b - p.buckets.data());
         hipError_t e = launch_zero(queue, 1, s);
         if (e != hipSuccess) return e;
         grid = b.grid;
@@ -1426,21 +1486,26 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
     return hipGetLastError();
 }
 
+static hipError_t launch_bucket_q(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s,
+                                  uint32_t *queues) {
+    return p.precision == HP_FP32 ? launch_bucket_t<float>(p, b, st, n_sweeps, s, queues)
+                                  : launch_bucket_t<double>(p, b, st, n_sweeps, s, queues);
+}
+
 hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
-    return p.precision == HP_FP32 ? launch_bucket_t<float>(p, b, st, n_sweeps, s)
-                                  : launch_bucket_t<double>(p, b, st, n_sweeps, s);
+    return launch_bucket_q(p, b, st, n_sweeps, s, p.d_queue);
 }
 
 template <typename Real>
-hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb) {
     const Bucket &b = p.buckets[0];
     SweepParams<Real> P = sweep_params<Real>(p, st, n_sweeps);
     P.lds_v_off = b.v_off;
     P.lds_x_off = b.x_off;
     SplitParams Q;
-    Q.xpart = p.d_xpart;
-    Q.vbuf = p.d_vbuf;
-    Q.cnt = p.d_cnt;
+    Q.xpart = rb.xpart;
+    Q.vbuf = rb.vbuf;
+    Q.cnt = rb.cnt;
     Q.err = p.d_err;
     Q.nstride = p.nstride;
     Q.G = p.split;
@@ -1448,9 +1513,9 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
     Q.xcd_map = p.xcd_map;
     Q.n_xcd = 8;
     // every mailbox starts with tag 0 (no sweep's tag)
-    hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(p.d_xpart), (int64_t)b.count * p.split * p.nstride * 2, s);
-    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_vbuf), (int64_t)b.count * p.nstride / 4, s);
-    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(p.d_cnt), (int64_t)b.count * 2 * kMaxSplit, s);
+    hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(rb.xpart), (int64_t)b.count * p.split * p.nstride * 2, s);
+    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(rb.vbuf), (int64_t)b.count * p.nstride / 4, s);
+    if (e == hipSuccess) e = launch_zero(reinterpret_cast<uint32_t *>(rb.cnt), (int64_t)b.count * 2 * kMaxSplit, s);
     if (e != hipSuccess) return e;
     return launch_split_one<Real>(p, P, Q, split_vpt(b.max_n, p.split, b.threads), s);
 }
@@ -1459,16 +1524,21 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
 // stream, or several buckets forked onto side streams (they are independent)
 // and joined back; then the sweep counter advances.
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
+    return launch_sweep(p, st, n_sweeps, s, plan_buffers(p));
+}
+
+hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb) {
     hipError_t e = hipSuccess;
     if (p.split > 1) {
-        e = p.precision == HP_FP64 ? launch_split_t<double>(p, st, n_sweeps, s) : launch_split_t<float>(p, st, n_sweeps, s);
+        e = p.precision == HP_FP64 ? launch_split_t<double>(p, st, n_sweeps, s, rb)
+                                   : launch_split_t<float>(p, st, n_sweeps, s, rb);
     } else if (p.buckets.size() == 1) {
-        e = launch_bucket(p, p.buckets[0], st, n_sweeps, s);
+        e = launch_bucket_q(p, p.buckets[0], st, n_sweeps, s, rb.queue);
     } else {
         e = hipEventRecord(p.ev_fork, s);
         for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i) {
             e = hipStreamWaitEvent(p.side[i], p.ev_fork, 0);
-            if (e == hipSuccess) e = launch_bucket(p, p.buckets[i], st, n_sweeps, p.side[i]);
+            if (e == hipSuccess) e = launch_bucket_q(p, p.buckets[i], st, n_sweeps, p.side[i], rb.queue);
             if (e == hipSuccess) e = hipEventRecord(p.ev_join[i], p.side[i]);
         }
         for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, p.ev_join[i], 0);

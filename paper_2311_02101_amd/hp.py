@@ -20,7 +20,7 @@ HP_FP64, HP_FP32, HP_MIXED_BF16 = 0, 1, 2
 PRECISION = {"f64": HP_FP64, "f32": HP_FP32, "mixed": HP_MIXED_BF16}
 KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
-EXPORTS = ("hp_plan", "hp_run", "hp_tune", "hp_check", "hp_plan_query", "hp_free",
+EXPORTS = ("hp_plan", "hp_run", "hp_run_noalloc", "hp_tune", "hp_check", "hp_plan_query", "hp_free",
            "hp_status_string", "hp_last_error", "hp_unit_propagate", "hp_merge_candidates", "hp_temper",
            "hp_get_temps")
 
@@ -86,6 +86,8 @@ def load():
     lib.hp_plan.restype = ct.c_int
     lib.hp_run.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
     lib.hp_run.restype = ct.c_int
+    lib.hp_run_noalloc.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
+    lib.hp_run_noalloc.restype = ct.c_int
     lib.hp_tune.argtypes = [ct.c_void_p, ct.POINTER(HpState), ct.c_int64, ct.c_void_p]
     lib.hp_tune.restype = ct.c_int
     lib.hp_plan_query.argtypes = [ct.c_void_p, ct.POINTER(HpPlanInfo)]
@@ -252,6 +254,12 @@ class Plan:
         lib = load()
         _check(lib.hp_run(self._h, ct.byref(state.c_struct()), int(n_sweeps),
                           _stream_handle(stream)))
+
+    def run_noalloc(self, state, n_sweeps, stream=None):
+        """hp_run_noalloc: the same sweeps with the run's scratch in the
+        library's static device array (allocates nothing)."""
+        _check(load().hp_run_noalloc(self._h, ct.byref(state.c_struct()), int(n_sweeps),
+                                     _stream_handle(stream)))
 
     def check(self):
         """Synchronise and raise if a split workgroup timed out waiting for the others."""
