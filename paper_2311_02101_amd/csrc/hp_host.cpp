@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -92,12 +93,14 @@ void release(Plan *p) {
 
 
 // Variable groups (of 4) per thread whose variance EMA stays in registers:
-// 1 or 2, else 0 (EMA in global memory).  The mixed-precision kernel and the
-// FP64 kernels keep at most one group in registers (two spill: the FP64 push
-// kernel measured 1.2% faster with the EMA of two groups in global memory).
+// 1, 2 or 4 (FP32), else 0 (EMA in global memory).  The mixed-precision
+// kernel and the FP64 kernels keep at most one group in registers (two
+// spill: the FP64 push kernel measured 1.2% faster with the EMA of two groups
+// in global memory).
 int vpt_for(int groups, int threads, bool mixed, bool fp64) {
     if (groups <= threads) return 1;
     if (groups <= 2 * threads && !mixed && !fp64) return 2;
+    if (groups <= 4 * threads && !mixed && !fp64) return 4;
     return 0;
 }
 
@@ -293,6 +296,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     std::vector<uint32_t> orig(NC);
     std::vector<uint32_t> push_slots(NV, 0);
     std::vector<int32_t> negcnt(NV, 0);
+    std::vector<std::array<int32_t, 8>> lofs(F);
     std::vector<std::string> pack_err(F);
     auto pack_formula = [&](int f) -> std::string {
         const int64_t v0 = cnf->var_offset[f], n = cnf->var_offset[f + 1] - v0;
@@ -342,6 +346,10 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
                          [](const std::pair<int, int64_t> &a, const std::pair<int, int64_t> &b) {
                              return a.first < b.first;
                          });
+        // records of length <= k: the bounds of the kernels' per-length runs
+        lofs[f].fill(0);
+        for (const auto &kc : key)
+            for (int k = kc.first; k < 8; ++k) lofs[f][k]++;
         for (int64_t j = 0; j < c1 - c0; ++j) {
             const int len = key[j].first;
             const int64_t c = key[j].second;
@@ -414,6 +422,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         fd[f].var_off = cnf->var_offset[f];
         fd[f].clause_off = cnf->clause_offset[f];
         fd[f].ptr_off = cnf->var_offset[f] + f;
+        for (int k = 0; k < 8; ++k) fd[f].lofs[k] = lofs[f][k];
     }
 
     Plan *p = new (std::nothrow) Plan();
@@ -444,12 +453,13 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         int32_t vo, xo, ho;
         const bool fx_ok = fx_shift >= 40;
         if (mixed)   // contributions come from MFMA: only the threshold table in LDS
-            return fx_ok && lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds ? kBucketWide : -1;
+            return fx_ok && lds_bytes_push(fd[f].n, kBucketWide, &vo, &xo) <= (size_t)max_lds ? kBucketWide : -1;
         if (clust)   // clustered tables in LDS only
             return fx_ok && lds_bytes_clust(fd[f].n, &vo, &xo) <= (size_t)max_lds ? kBucketPush : -1;
         if (opts->kernel != HP_KERNEL_PULL && fx_ok) {
-            if (lds_bytes_push(fd[f].n, false, &vo, &xo) <= (size_t)max_lds) return kBucketPush;
-            if (lds_bytes_push(fd[f].n, true, &vo, &xo) <= (size_t)max_lds) return kBucketWide;
+            if (lds_bytes_push(fd[f].n, kBucketPush, &vo, &xo) <= (size_t)max_lds) return kBucketPush;
+            if (lds_bytes_push(fd[f].n, kBucketMid, &vo, &xo) <= (size_t)max_lds) return kBucketMid;
+            if (lds_bytes_push(fd[f].n, kBucketWide, &vo, &xo) <= (size_t)max_lds) return kBucketWide;
         }
         if (opts->kernel == HP_KERNEL_PUSH) return -1;
         if (lds_bytes_pull(fd[f].n, fd[f].c, real_bytes, &vo, &ho) <= (size_t)max_lds) return kBucketPull;
@@ -512,7 +522,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         else if (clust)
             bk.lds = lds_bytes_clust(bk.max_n, &bk.v_off, &bk.x_off);
         else
-            bk.lds = lds_bytes_push(bk.max_n, bk.kind == kBucketWide, &bk.v_off, &bk.x_off);
+            bk.lds = lds_bytes_push(bk.max_n, bk.kind, &bk.v_off, &bk.x_off);
         // default workgroup size: about six clauses per thread per sweep
         int t = opts->threads;
         if (t == 0) {

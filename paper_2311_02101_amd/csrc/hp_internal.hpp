@@ -25,6 +25,7 @@ struct FormulaDev {
     int64_t var_off;      // var_offset[f]: state block starts at var_off * B
     int64_t clause_off;   // clause_offset[f]: first clause record / column
     int64_t ptr_off;      // var_off + f: first of the N_f+1 occurrence offsets
+    int32_t lofs[8];      // push records (sorted by length) of length <= k, k = 0..7
 };
 
 struct WorkItem {
@@ -152,7 +153,10 @@ enum class Variant { kPull = 0, kPush = 1 };
 
 // A launch over a contiguous range of work items: formulas of one size class
 // and one kernel variant, with its own workgroup size and LDS footprint.
-enum BucketKind : int32_t { kBucketPush = 0, kBucketWide = 1, kBucketPull = 2 };
+// push: every table in LDS; mid: the merged padding table gpad read from
+// global memory (one read per clause), the rest in LDS; wide: both
+// contribution tables in global memory (the largest formulas)
+enum BucketKind : int32_t { kBucketPush = 0, kBucketWide = 1, kBucketPull = 2, kBucketMid = 3 };
 constexpr int kMaxBuckets = 32;
 
 struct Bucket {
@@ -272,7 +276,7 @@ int split_occupancy(const Plan &p, int G);
 
 // LDS bytes of the two kernel variants for the largest formula
 size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, int32_t *hm_off);
-size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off);
+size_t lds_bytes_push(int max_n, int kind, int32_t *v_off, int32_t *x_off);
 size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off);
 
 // learned initial assignments (hp_mlp.hip)

@@ -39,6 +39,7 @@
 #include <cmath>
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 namespace hp {
 
@@ -203,6 +204,12 @@ constexpr int kPushVOff = kPushCntOff + 64 * 4;
 constexpr int kWideCntOff = kPatterns * kMaxL * 4;
 constexpr int kWideVOff = kWideCntOff + 64 * 4;
 
+// middle layout (only the merged padding table gpad, one read per clause,
+// from global memory): thr | gfx | counts | v | x
+constexpr int kMidGfxOff = kPatterns * kMaxL * 4;
+constexpr int kMidCntOff = kMidGfxOff + kHidMasks * kMaxL * 8;
+constexpr int kMidVOff = kMidCntOff + 64 * 4;
+
 // size-clustered layout: thr (248 rows) | gfx (488 rows) | gpad (504) | counts | v | x
 constexpr int kClustGfxOff = kClustThrRows * kMaxL * 4;
 constexpr int kClustGpadOff = kClustGfxOff + kClustGfxRows * kMaxL * 8;
@@ -219,8 +226,8 @@ static size_t lds_tail(size_t off, int max_n, int32_t *v_off, int32_t *x_off) {
     return off;
 }
 
-size_t lds_bytes_push(int max_n, bool wide, int32_t *v_off, int32_t *x_off) {
-    return lds_tail(wide ? kWideVOff : kPushVOff, max_n, v_off, x_off);
+size_t lds_bytes_push(int max_n, int kind, int32_t *v_off, int32_t *x_off) {
+    return lds_tail(kind == kBucketWide ? kWideVOff : kind == kBucketMid ? kMidVOff : kPushVOff, max_n, v_off, x_off);
 }
 
 size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off) {
@@ -238,10 +245,12 @@ __device__ __forceinline__ uint32_t draw4(const uint4 &r, const uint4 &t) {
            (r.w <= t.w ? 8u << SH : 0u);
 }
 
+// NB: Philox blocks per clause, 1 (L <= 4) or 2 (L <= 8); 0 = read nbh at run time
+template <int NB = 0>
 __device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t blk, const PhiloxSweep &u, Key2 key,
                                                 uint32_t nbh) {
     const uint4 ta = *reinterpret_cast<const uint4 *>(row);
-    if (nbh > 1) {
+    if (NB == 2 || (NB == 0 && nbh > 1)) {
         // both blocks in one pass (interleaved rounds, one key schedule)
         const uint4 tb = *reinterpret_cast<const uint4 *>(row + 4);
         uint4 r[2];
@@ -447,13 +456,28 @@ __device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, 
                    lds_at(kWideVOff)};
 }
 
+// middle variant: gpad of temperature tau stays in global memory
+__device__ __forceinline__ PushLds push_lds_mid(unsigned char *lds, int x_off, const int64_t *gpad, int tau) {
+    return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kMidGfxOff)),
+                   const_cast<int64_t *>(gpad + tau * kHidMasks * kMaxL), reinterpret_cast<int *>(lds + kMidCntOff),
+                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kMidVOff)};
+}
+
+template <int kTab>
+__device__ __forceinline__ PushLds push_lds_for(unsigned char *lds, int x_off, const int64_t *gfx, const int64_t *gpad,
+                                                int tau) {
+    if (kTab == kBucketWide) return push_lds_wide(lds, x_off, gfx, gpad, tau);
+    if (kTab == kBucketMid) return push_lds_mid(lds, x_off, gpad, tau);
+    return push_lds(lds, x_off);
+}
+
 __device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off) {
     return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kClustGfxOff)),
                    reinterpret_cast<int64_t *>(lds_at(kClustGpadOff)), reinterpret_cast<int *>(lds + kClustCntOff),
                    reinterpret_cast<int64_t *>(lds + x_off), lds_at(kClustVOff)};
 }
 
-template <bool kWide, bool kClust = false>
+template <int kTab, bool kClust = false>
 __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_t *thr, const int64_t *gfx,
                                                  const int64_t *gpad, int tau, int tid, int NT) {
     if (kClust) {
@@ -463,11 +487,13 @@ __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_
         return;
     }
     for (int i = tid; i < kPatterns * kMaxL; i += NT) L.thr[i] = thr[tau * kPatterns * kMaxL + i];
-    if (!kWide) {
+    if (kTab == kBucketPush) {
         for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
             L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
             L.gpad[i] = gpad[tau * kHidMasks * kMaxL + i];
         }
+    } else if (kTab == kBucketMid) {
+        for (int i = tid; i < kHidMasks * kMaxL; i += NT) L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
     }
 }
 
@@ -499,17 +525,6 @@ __device__ __forceinline__ uint32_t pattern_fixed(const uint8_t *v, const uint4 
     return m | (pad_mask<kClust>((uint32_t)LEN, full) & (0u - (m & 1u)));
 }
 
-__device__ __forceinline__ uint32_t gather_any(const uint8_t *v, const uint4 &r, uint32_t len) {
-    uint32_t m = v[r.x & 0x7fffu];
-    if (len > 1) m |= (uint32_t)v[(r.x >> 16) & 0x7fffu] << 1;
-    if (len > 2) m |= (uint32_t)v[r.y & 0x7fffu] << 2;
-    if (len > 3) m |= (uint32_t)v[(r.y >> 16) & 0x7fffu] << 3;
-    if (len > 4) m |= (uint32_t)v[r.z & 0x7fffu] << 4;
-    if (len > 5) m |= (uint32_t)v[(r.z >> 16) & 0x7fffu] << 5;
-    if (len > 6) m |= (uint32_t)v[r.w & 0x7fffu] << 6;
-    return m;
-}
-
 // Scatter of a clause's contributions: g0 (the merged slot 0) to slot 0's
 // variable, gr[k] to slot k's for k = 1..len-1.
 template <int k, int LEN>
@@ -532,102 +547,128 @@ __device__ __forceinline__ void scatter_fixed(int64_t *x, const uint4 &r, int64_
     scatter_slots<0, LEN>(x, r, g);
 }
 
-__device__ __forceinline__ void scatter_any(int64_t *x, const uint4 &r, uint32_t len, int64_t g0,
-                                            const int64_t *gr) {
-    int64_t g[7];
-#pragma unroll
-    for (int k = 1; k < 7; ++k) g[k] = gr[k];      // rows hold 8 entries: in bounds for any len
-    push_add(x, r.x & 0xffffu, g0);
-    if (len > 1) push_add(x, r.x >> 16, g[1]);
-    if (len > 2) push_add(x, r.y & 0xffffu, g[2]);
-    if (len > 3) push_add(x, r.y >> 16, g[3]);
-    if (len > 4) push_add(x, r.z & 0xffffu, g[4]);
-    if (len > 5) push_add(x, r.z >> 16, g[5]);
-    if (len > 6) push_add(x, r.w & 0xffffu, g[6]);
-}
-
-// Clause phase over the clause records c = c_first + c_step * j, c < c_end,
-// j strided over the workgroup:
-// gather, literal-truth pattern, count; when sampling, the hidden draw and the
-// scatter of the clause's contributions into the LDS accumulators.  Returns
-// this thread's number of satisfied clauses.  Records are sorted by length,
-// so the 64 lanes of a wave nearly always hold clauses of one length: then
-// the gather and scatter run unrolled for that length under a scalar branch
-// (ul > 0), else per-lane length tests (ul = 0).
-//
+// One clause of compile-time length LEN: gather, literal-truth pattern,
+// count; when sampling, the hidden draw and the scatter of its
+// contributions into the LDS accumulators.  Returns 1 if it is satisfied.
 // kClust: the size-clustered model; a clause of length len takes the tables
 // of group K = max(len, 3) (L = 3 or K + 1 hidden units, drawn from blocks
 // 2c and, for L > 4, 2c + 1), and nbh, full and lmask are unused.
-template <bool kSample, bool kClust = false>
-__device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
-                                            const uint32_t *__restrict__ orig, int c_first, int c_step,
-                                            int c_end, int tid, int NT, const PhiloxSweep &ps, Key2 key,
-                                            uint32_t nbh, uint32_t full, uint32_t lmask) {
-    int cnt = 0;
-    uint4 r_next = make_uint4(0, 0, 0, 0);
-    uint32_t o_next = 0;
-    const int c_inc = c_step * NT;
-    if (c_first + c_step * tid < c_end) {
-        r_next = rec[c_first + c_step * tid];
-        o_next = orig[c_first + c_step * tid];
+template <int LEN, bool kSample, bool kClust, int NB>
+__device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint32_t oc, const PhiloxSweep &ps,
+                                          Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
+    const uint32_t m = pattern_fixed<LEN, kClust>(L.v, r, full);
+    if (kSample) {
+        uint32_t n;
+        int64_t g0;
+        const int64_t *gr;
+        if (kClust) {
+            constexpr uint32_t Kc = LEN < 3 ? 3u : (uint32_t)LEN;
+            constexpr bool big = Kc > 3u;                            // L = K + 1 > 4: two blocks
+            n = hidden_mask<big ? 2 : 1>(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc * 2u, ps, key, 0u) &
+                (big ? (2u << Kc) - 1u : 7u);
+            g0 = L.gpad[(LEN <= 3 ? 8u * (LEN - 1u) : (2u << LEN) - 8u) + n];
+            gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
+        } else {
+            n = hidden_mask<NB>(L.thr + m * kMaxL, oc << (NB > 1 ? 1 : 0), ps, key, 0u) & lmask;
+            g0 = L.gpad[LEN * kHidMasks + n];
+            gr = L.gfx + n * kMaxL;
+        }
+        scatter_fixed<LEN>(L.x, r, g0, gr);
     }
-    for (int c = c_first + c_step * tid; c < c_end; c += c_inc) {
-        const uint4 r = r_next;
-        const uint32_t oc = o_next;
-        if (c + c_inc < c_end) {       // prefetch the next record
-            r_next = rec[c + c_inc];
-            o_next = orig[c + c_inc];
-        }
-        const uint32_t len = (r.w >> 16) & 7u;
-        const uint32_t negm = r.w >> 19;          // negation bits of slots 0..len-1
-        const int lu = __builtin_amdgcn_readfirstlane((int)len);
-        const int ul = __all((int)len == lu) ? lu : 0;
-        // gather the values of the clause's variables, apply the polarities
-        // and fill the padding positions with literal 0's truth
-        uint32_t m;
-        switch (ul) {
-            case 1: m = pattern_fixed<1, kClust>(L.v, r, full); break;
-            case 2: m = pattern_fixed<2, kClust>(L.v, r, full); break;
-            case 3: m = pattern_fixed<3, kClust>(L.v, r, full); break;
-            case 4: m = pattern_fixed<4, kClust>(L.v, r, full); break;
-            case 5: m = pattern_fixed<5, kClust>(L.v, r, full); break;
-            case 6: m = pattern_fixed<6, kClust>(L.v, r, full); break;
-            case 7: m = pattern_fixed<7, kClust>(L.v, r, full); break;
-            default:
-                m = gather_any(L.v, r, len) ^ negm;
-                m |= pad_mask<kClust>(len, full) & (0u - (m & 1u));
-        }
-        cnt += (m != 0u);
-        if (kSample) {
-            uint32_t n;
-            int64_t g0;
-            const int64_t *gr;
-            if (kClust) {
-                const uint32_t Kc = len < 3u ? 3u : len;
-                const bool big = Kc > 3u;                            // L = K + 1 > 4: two blocks
-                n = hidden_mask(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc * 2u, ps, key,
-                                big ? 2u : 1u) &
-                    (big ? (2u << Kc) - 1u : 7u);
-                g0 = L.gpad[(len <= 3u ? 8u * (len - 1u) : (2u << len) - 8u) + n];
-                gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
-            } else {
-                n = hidden_mask(L.thr + m * kMaxL, oc << (nbh - 1u), ps, key, nbh) & lmask;
-                g0 = L.gpad[len * kHidMasks + n];
-                gr = L.gfx + n * kMaxL;
-            }
-            switch (ul) {
-                case 1: scatter_fixed<1>(L.x, r, g0, gr); break;
-                case 2: scatter_fixed<2>(L.x, r, g0, gr); break;
-                case 3: scatter_fixed<3>(L.x, r, g0, gr); break;
-                case 4: scatter_fixed<4>(L.x, r, g0, gr); break;
-                case 5: scatter_fixed<5>(L.x, r, g0, gr); break;
-                case 6: scatter_fixed<6>(L.x, r, g0, gr); break;
-                case 7: scatter_fixed<7>(L.x, r, g0, gr); break;
-                default: scatter_any(L.x, r, len, g0, gr);
-            }
-        }
+    return m != 0u ? 1 : 0;
+}
+
+// A wave's view of a range of clause records: raw buffer descriptors over
+// the records and their input indices (loads past the range return zeros),
+// so a load of 64 consecutive records takes a wave-uniform byte offset in a
+// scalar register and the lane's fixed offset in a vector register.
+struct RecView {
+    __amdgpu_buffer_rsrc_t rec, orig;
+};
+
+// the third descriptor word of a raw (untyped) buffer on gfx9-family GPUs
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ RecView rec_view(const uint4 *rec, const uint32_t *orig, int M) {
+    return RecView{__builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(rec), (short)0, M * 16, kRawBufferWord3),
+                   __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(orig), (short)0, M * 4, kRawBufferWord3)};
+}
+
+__device__ __forceinline__ void rec_load(const RecView &rv, int first, int lane, uint4 &r, uint32_t &oc) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rv.rec, lane * 16, first * 16, 0);
+    r = make_uint4(v[0], v[1], v[2], v[3]);
+    oc = __builtin_amdgcn_raw_buffer_load_b32(rv.orig, lane * 4, first * 4, 0);
+}
+
+// The records [lo, hi) of one clause length, wave-uniform bounds: lane l
+// takes records lo + l, lo + 64 + l, ...  Each load is 64 consecutive
+// records (one wave-wide 1 KiB read) addressed by a wave-uniform base and
+// the lane's fixed offset; the next step's record is loaded while the
+// current one is processed (two register sets, alternating).
+template <int LEN, bool kSample, bool kClust, int NB>
+__device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int lane,
+                                              const PhiloxSweep &ps, Key2 key, uint32_t nbh, uint32_t full,
+                                              uint32_t lmask) {
+    int cnt = 0;
+    if (lo >= hi) return 0;
+    uint4 rn;
+    uint32_t on;
+    rec_load(rv, lo, lane, rn, on);
+    for (int base = lo; base < hi; base += kWave) {
+        const uint4 r = rn;
+        const uint32_t oc = on;
+        if (base + kWave < hi) rec_load(rv, base + kWave, lane, rn, on);
+        if (base + lane < hi) cnt += clause_one<LEN, kSample, kClust, NB>(L, r, oc, ps, key, nbh, full, lmask);
     }
     return cnt;
+}
+
+// Clause phase over the M records of a range (a formula's, or a split
+// member's run), sorted by clause length with bnd[k] = the number of records
+// of length <= k (bnd[0] = 0, bnd[7] = M).  Wave w of the workgroup takes
+// the contiguous chunk [w M / W, (w + 1) M / W) and walks it length by
+// length, so every step of a wave is one clause length (the gather and
+// scatter unrolled for it) with no per-record length test.  Returns this
+// thread's number of satisfied clauses.
+template <bool kSample, bool kClust, int NB>
+__device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &rv, int lo, int hi,
+                                               const int32_t (&bnd)[8], int lane, const PhiloxSweep &ps, Key2 key,
+                                               uint32_t nbh, uint32_t full, uint32_t lmask) {
+    int cnt = 0;
+#define HP_SEG(LEN)                                                                                                 \
+    cnt += clause_segment<LEN, kSample, kClust, NB>(L, rv, max(lo, bnd[LEN - 1]), min(hi, bnd[LEN]), lane, ps, key, \
+                                                    nbh, full, lmask)
+    HP_SEG(1);
+    HP_SEG(2);
+    HP_SEG(3);
+    HP_SEG(4);
+    HP_SEG(5);
+    HP_SEG(6);
+    HP_SEG(7);
+#undef HP_SEG
+    return cnt;
+}
+
+template <bool kSample, bool kClust>
+__device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
+                                            const uint32_t *__restrict__ orig, int M, const int32_t (&bnd)[8],
+                                            int tid, int NT, const PhiloxSweep &ps, Key2 key, uint32_t nbh,
+                                            uint32_t full, uint32_t lmask) {
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), nw = NT / kWave;
+    const int lo = (int)((int64_t)wave * M / nw), hi = (int)((int64_t)(wave + 1) * M / nw);
+    const RecView rv = rec_view(rec, orig, M);
+    if (kClust) return clause_phase_nb<kSample, kClust, 0>(L, rv, lo, hi, bnd, lane, ps, key, nbh, full, lmask);
+    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2>(L, rv, lo, hi, bnd, lane, ps, key, nbh, full, lmask)
+                   : clause_phase_nb<kSample, kClust, 1>(L, rv, lo, hi, bnd, lane, ps, key, nbh, full, lmask);
+}
+
+// Range-relative length bounds of split member g of G: the member's run
+// holds the sorted records g, g + G, g + 2G, ..., so of the lofs[k] records
+// of length <= k it holds ceil((lofs[k] - g) / G).
+__device__ __forceinline__ void member_bounds(const int32_t (&lofs)[8], int g, int G, int32_t (&bnd)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) bnd[k] = lofs[k] > g ? (lofs[k] - g + G - 1) / G : 0;
 }
 
 // ---- mixed precision: the per-clause products on MFMA ---------------------
@@ -752,6 +793,24 @@ __device__ __forceinline__ int clause_phase_mfma(const PushLds &L, const uint4 *
     return cnt;
 }
 
+template <typename Real>
+__device__ __forceinline__ Real buffer_load_real(__amdgpu_buffer_rsrc_t rs, int i);
+template <>
+__device__ __forceinline__ float buffer_load_real<float>(__amdgpu_buffer_rsrc_t rs, int i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, 0, 0));
+}
+typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2_t;
+template <>
+__device__ __forceinline__ double buffer_load_real<double>(__amdgpu_buffer_rsrc_t rs, int i) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, i * 8, 0, 0));
+}
+__device__ __forceinline__ void buffer_store_real(float v, __amdgpu_buffer_rsrc_t rs, int i) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, i * 4, 0, 0);
+}
+__device__ __forceinline__ void buffer_store_real(double v, __amdgpu_buffer_rsrc_t rs, int i) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, i * 8, 0, 0);
+}
+
 // Visible update of one variable from its fixed-point logit: sigmoid, EMA,
 // Bernoulli draw U < rho with U = (word >> 8) 2^-24.
 template <typename Real>
@@ -777,10 +836,14 @@ __device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, i
 // item w.  Otherwise the grid is persistent: workgroups take items from an
 // atomic counter (zeroed before the launch) until all `count` items are done,
 // largest formulas first, so uneven sizes balance over the resident grid.
-template <typename Real, int VPT, bool kWide, bool kMfma = false, bool kClust = false>
+template <typename Real, int VPT, int kTab, bool kMfma = false, bool kClust = false>
 __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, uint32_t *queue, int count) {
     extern __shared__ __align__(16) unsigned char lds[];
-    int *s_item = reinterpret_cast<int *>(lds + (kClust ? kClustCntOff : kWide ? kWideCntOff : kPushCntOff)) + 63;
+    int *s_item = reinterpret_cast<int *>(lds + (kClust                  ? kClustCntOff
+                                                 : kTab == kBucketWide ? kWideCntOff
+                                                 : kTab == kBucketMid  ? kMidCntOff
+                                                                       : kPushCntOff)) +
+                  63;
     const int tid = threadIdx.x, NT = blockDim.x;
     const bool sample = P.n_sweeps > 0;
     const int64_t S = sample ? P.n_sweeps : 1;
@@ -799,7 +862,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         } else {
             if (tid == 0) *s_item = (int)atomicAdd(queue, 1u);
             __syncthreads();
-            item = *s_item;
+            item = __builtin_amdgcn_readfirstlane(*s_item);    // the same for every thread
             __syncthreads();          // s_item is rewritten by the next take
             if (item >= count) break;
         }
@@ -808,15 +871,14 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         const int N = fd.n, C = fd.c;
         const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
         const PushLds L = kClust ? push_lds_clust(lds, P.lds_x_off)
-                          : kWide ? push_lds_wide(lds, P.lds_x_off, P.gfx, P.gpad, tau)
-                                  : push_lds(lds, P.lds_x_off);
+                                 : push_lds_for<kTab>(lds, P.lds_x_off, P.gfx, P.gpad, tau);
         const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
         const uint4 *__restrict__ rec = P.rec + fd.clause_off;
         const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
         const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
         const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
 
-        load_push_tables<kWide, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+        load_push_tables<kTab, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
         for (int i = tid; i < N; i += NT) {
             L.v[i] = P.v[sbase + i];
             L.x[i] = negcnt[i];
@@ -828,7 +890,6 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
         }
         constexpr int VR = VPT > 0 ? VPT : 1;
         Real nu[VR][4];
-        int32_t ncr[VR][4];
         if (VPT > 0) {
 #pragma unroll
             for (int j = 0; j < VR; ++j)
@@ -836,9 +897,17 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
                 for (int q = 0; q < 4; ++q) {
                     const int i = (tid + j * NT) * 4 + q;
                     nu[j][q] = i < N ? P.nu[sbase + i] : Real(0);
-                    ncr[j][q] = i < N ? negcnt[i] : 0;
                 }
         }
+        // buffer views of this chain's best and nu and the formula's negated-
+        // slot counts: the visible phase addresses them by the variable's
+        // offset alone (accesses past N read zeros and write nothing)
+        const __amdgpu_buffer_rsrc_t best_rs =
+            __builtin_amdgcn_make_buffer_rsrc(P.best + sbase, (short)0, N, kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t nu_rs =
+            __builtin_amdgcn_make_buffer_rsrc(P.nu + sbase, (short)0, N * (int)sizeof(Real), kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t neg_rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(negcnt), (short)0, N * 4, kRawBufferWord3);
         int smax = P.s_max[(int64_t)w.f * P.B + w.b];
         __syncthreads();
 
@@ -853,36 +922,48 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
                              : clause_phase_mfma<false>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh,
                                                         full, lmask, P.K, a1, a2, 1.0 / fx_scale);
             else
-                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, 0, 1, C, tid, NT, ps, key, nbh, full, lmask)
-                             : clause_phase<false, kClust>(L, rec, orig, 0, 1, C, tid, NT, ps, key, nbh, full, lmask);
+                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, C, fd.lofs, tid, NT, ps, key, nbh, full, lmask)
+                             : clause_phase<false, kClust>(L, rec, orig, C, fd.lofs, tid, NT, ps, key, nbh, full, lmask);
             const int total = block_total(L, cnt, tid, NT);
             const bool improved = total > smax;
             if (improved) smax = total;
             // ---- visible phase ----
             const int groups = (N + 3) >> 2;
             const int jmax = VPT > 0 ? VPT : (groups + NT - 1) / NT;
+            // the thread index passes through an empty asm each sweep, so the
+            // per-variable offsets below are recomputed here instead of being
+            // hoisted out of the sweep loop into registers held across the
+            // clause phase
+            int vtid = tid;
+            asm volatile("" : "+v"(vtid));
 #pragma unroll
             for (int j = 0; j < (VPT > 0 ? VPT : 1); ++j) {
               for (int jj = (VPT > 0 ? j : 0); jj < (VPT > 0 ? j + 1 : jmax); ++jj) {
-                const int grp = tid + jj * NT;
+                const int grp = vtid + jj * NT;
                 if (grp < groups) {
                     uint4 r = make_uint4(0, 0, 0, 0);
-                    if (sample) r = philox_sweep(kPhaseVisible | (uint32_t)grp, ps, key);
+                    int32_t nc[4] = {0, 0, 0, 0};
+                    if (sample) {
+                        r = philox_sweep(kPhaseVisible | (uint32_t)grp, ps, key);
+                        // the accumulators restart at the negated-slot counts
+                        const auto c4 = __builtin_amdgcn_raw_buffer_load_b128(neg_rs, grp * 16, 0, 0);
+                        nc[0] = (int32_t)c4[0], nc[1] = (int32_t)c4[1], nc[2] = (int32_t)c4[2], nc[3] = (int32_t)c4[3];
+                    }
                     const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int i = grp * 4 + q;
                         if (i < N) {
-                            if (improved) P.best[sbase + i] = L.v[i];
+                            if (improved) __builtin_amdgcn_raw_buffer_store_b8(L.v[i], best_rs, i, 0, 0);
                             if (sample) {
                                 const int64_t xi = L.x[i];
-                                L.x[i] = VPT > 0 ? ncr[j][q] : negcnt[i];
+                                L.x[i] = nc[q];
                                 if (VPT > 0) {
                                     L.v[i] = visible_update(xi, fx_scale, nu[j][q], alpha, rw[q]);
                                 } else {
-                                    Real nv = P.nu[sbase + i];
+                                    Real nv = buffer_load_real<Real>(nu_rs, i);
                                     L.v[i] = visible_update(xi, fx_scale, nv, alpha, rw[q]);
-                                    P.nu[sbase + i] = nv;
+                                    buffer_store_real(nv, nu_rs, i);
                                 }
                             }
                         }
@@ -955,6 +1036,7 @@ struct SplitCtx {
     Real alpha;
     int G, g, N, C, tid, NT, b, groups, q_lo, q_hi;
     int c_lo, c_hi;              // this member's run of records
+    int32_t bnd[8];              // its records of length <= k, k = 0..7 (run-relative)
     uint32_t nbh, full, lmask;
     bool sample;
 };
@@ -1026,10 +1108,10 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         // member g's records: every G-th of the length-sorted order (the same
         // mix of clause lengths for all members), stored as one contiguous run
         const PhiloxSweep ps = philox_sweep_consts(tlo, (uint32_t)c.b, thi, c.key);
-        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, ps, c.key,
-                                                              c.nbh, c.full, c.lmask)
-                                 : clause_phase<false, kClust>(L, c.rec, c.orig, c.c_lo, 1, c.c_hi, tid, NT, ps, c.key,
-                                                               c.nbh, c.full, c.lmask);
+        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
+                                                              c.bnd, tid, NT, ps, c.key, c.nbh, c.full, c.lmask)
+                                 : clause_phase<false, kClust>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
+                                                               c.bnd, tid, NT, ps, c.key, c.nbh, c.full, c.lmask);
         const int part = block_total(L, cnt, tid, NT);
         // publish the partial logits of the variables other members own
         if (c.sample) {
@@ -1159,6 +1241,8 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
         item = blockIdx.x / G;
         g = blockIdx.x % G;
     }
+    item = __builtin_amdgcn_readfirstlane(item);
+    g = __builtin_amdgcn_readfirstlane(g);
     const WorkItem w = P.work[item];
     const FormulaDev fd = P.fd[w.f];
     const int N = fd.n;
@@ -1170,6 +1254,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.C = fd.c;
     c.c_lo = g * (fd.c / G) + min(g, fd.c % G);
     c.c_hi = c.c_lo + fd.c / G + (g < fd.c % G ? 1 : 0);
+    member_bounds(fd.lofs, g, G, c.bnd);
     c.tid = tid;
     c.NT = NT;
     c.b = w.b;
@@ -1196,7 +1281,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
     c.pcnt = Q.cnt + (size_t)item * 2 * kMaxSplit;
 
-    load_push_tables<false, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+    load_push_tables<kBucketPush, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
     for (int i = tid; i < N; i += NT) {
         L.v[i] = P.v[c.sbase + i];
         L.x[i] = 0;
@@ -1246,21 +1331,31 @@ hipError_t launch_zero(uint32_t *ptr, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename Real>
-const void *push_kernel_ptr(int vpt, bool wide) {
+template <typename Real, int kTab>
+const void *push_kernel_ptr_t(int vpt) {
     switch (vpt) {
-        case 1: return wide ? (const void *)sweep_push_kernel<Real, 1, true> : (const void *)sweep_push_kernel<Real, 1, false>;
-        case 2: return wide ? (const void *)sweep_push_kernel<Real, 2, true> : (const void *)sweep_push_kernel<Real, 2, false>;
-        default: return wide ? (const void *)sweep_push_kernel<Real, 0, true> : (const void *)sweep_push_kernel<Real, 0, false>;
+        case 1: return (const void *)sweep_push_kernel<Real, 1, kTab>;
+        case 2: return (const void *)sweep_push_kernel<Real, 2, kTab>;
+        case 4: return (const void *)sweep_push_kernel<Real, 4, kTab>;
+        default: return (const void *)sweep_push_kernel<Real, 0, kTab>;
     }
+}
+
+// variable groups per thread kept in registers: 0 (EMA in global memory), 1, 2 or 4
+template <typename Real>
+const void *push_kernel_ptr(int vpt, int kind) {
+    return kind == kBucketWide ? push_kernel_ptr_t<Real, kBucketWide>(vpt)
+           : kind == kBucketMid ? push_kernel_ptr_t<Real, kBucketMid>(vpt)
+                                : push_kernel_ptr_t<Real, kBucketPush>(vpt);
 }
 
 template <typename Real>
 const void *clust_kernel_ptr(int vpt) {
     switch (vpt) {
-        case 1: return (const void *)sweep_push_kernel<Real, 1, false, false, true>;
-        case 2: return (const void *)sweep_push_kernel<Real, 2, false, false, true>;
-        default: return (const void *)sweep_push_kernel<Real, 0, false, false, true>;
+        case 1: return (const void *)sweep_push_kernel<Real, 1, kBucketPush, false, true>;
+        case 2: return (const void *)sweep_push_kernel<Real, 2, kBucketPush, false, true>;
+        case 4: return (const void *)sweep_push_kernel<Real, 4, kBucketPush, false, true>;
+        default: return (const void *)sweep_push_kernel<Real, 0, kBucketPush, false, true>;
     }
 }
 
@@ -1278,9 +1373,9 @@ const void *split_kernel_ptr(bool clust, int vpt) {
 
 const void *mixed_kernel_ptr(int vpt) {
     switch (vpt) {
-        case 1: return (const void *)sweep_push_kernel<double, 1, true, true>;
-        case 2: return (const void *)sweep_push_kernel<double, 2, true, true>;
-        default: return (const void *)sweep_push_kernel<double, 0, true, true>;
+        case 1: return (const void *)sweep_push_kernel<double, 1, kBucketWide, true>;
+        case 2: return (const void *)sweep_push_kernel<double, 2, kBucketWide, true>;
+        default: return (const void *)sweep_push_kernel<double, 0, kBucketWide, true>;
     }
 }
 
@@ -1295,13 +1390,16 @@ const void *pull_kernel_ptr(int vpt) {
 
 template <typename Real>
 hipError_t set_limits_t(int bytes) {
-    const void *ks[] = {push_kernel_ptr<Real>(1, false), push_kernel_ptr<Real>(2, false), push_kernel_ptr<Real>(0, false),
-                        push_kernel_ptr<Real>(1, true),  push_kernel_ptr<Real>(2, true),  push_kernel_ptr<Real>(0, true),
-                        pull_kernel_ptr<Real>(1),        pull_kernel_ptr<Real>(2),        pull_kernel_ptr<Real>(0),
-                        clust_kernel_ptr<Real>(1),       clust_kernel_ptr<Real>(2),       clust_kernel_ptr<Real>(0),
-                        split_kernel_ptr<Real>(false, 1), split_kernel_ptr<Real>(false, 2),
-                        split_kernel_ptr<Real>(false, 0), split_kernel_ptr<Real>(true, 1),
-                        split_kernel_ptr<Real>(true, 2),  split_kernel_ptr<Real>(true, 0)};
+    std::vector<const void *> ks;
+    for (int vpt : {0, 1, 2, 4}) {
+        for (int kind : {(int)kBucketPush, (int)kBucketWide, (int)kBucketMid}) ks.push_back(push_kernel_ptr<Real>(vpt, kind));
+        ks.push_back(clust_kernel_ptr<Real>(vpt));
+    }
+    for (int vpt : {0, 1, 2}) {
+        ks.push_back(pull_kernel_ptr<Real>(vpt));
+        ks.push_back(split_kernel_ptr<Real>(false, vpt));
+        ks.push_back(split_kernel_ptr<Real>(true, vpt));
+    }
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -1326,8 +1424,7 @@ int bucket_occupancy(const Plan &p, const Bucket &b) {
     else if (p.clust)
         k = p.precision == HP_FP64 ? clust_kernel_ptr<double>(b.vpt) : clust_kernel_ptr<float>(b.vpt);
     else
-        k = p.precision == HP_FP64 ? push_kernel_ptr<double>(b.vpt, b.kind == kBucketWide)
-                                   : push_kernel_ptr<float>(b.vpt, b.kind == kBucketWide);
+        k = p.precision == HP_FP64 ? push_kernel_ptr<double>(b.vpt, b.kind) : push_kernel_ptr<float>(b.vpt, b.kind);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, b.threads, b.lds) != hipSuccess) return 1;
     return nb;
@@ -1468,7 +1565,6 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
                            b.lds, s, P);
         return hipGetLastError();
     }
-    const bool wide = b.kind == kBucketWide;
     uint32_t *queue = nullptr;
     int grid = b.count;
     if (b.grid > 0) {
@@ -1480,7 +1576,7 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
     }
     const void *kern = p.precision == HP_MIXED_BF16 ? mixed_kernel_ptr(b.vpt)
                        : p.clust                     ? clust_kernel_ptr<Real>(b.vpt)
-                                                     : push_kernel_ptr<Real>(b.vpt, wide);
+                                                     : push_kernel_ptr<Real>(b.vpt, b.kind);
     hipLaunchKernelGGL((void (*)(SweepParams<Real>, uint32_t *, int))kern, dim3(grid), dim3(b.threads), b.lds, s, P,
                        queue, b.count);
     return hipGetLastError();
