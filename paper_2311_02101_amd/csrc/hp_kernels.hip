@@ -600,44 +600,62 @@ __device__ __forceinline__ void rec_load(const RecView &rv, int first, int lane,
     oc = __builtin_amdgcn_raw_buffer_load_b32(rv.orig, lane * 4, first * 4, 0);
 }
 
-// The records [lo, hi) of one clause length, wave-uniform bounds: lane l
-// takes records lo + l, lo + 64 + l, ...  Each load is 64 consecutive
-// records (one wave-wide 1 KiB read) addressed by a wave-uniform base and
-// the lane's fixed offset; the next step's record is loaded while the
-// current one is processed (two register sets, alternating).
+// The steps of one clause length's run [lo, hi) that fall to this wave:
+// the run is cut into steps of 64 consecutive records, and the steps of all
+// the runs, numbered consecutively from `step0` for this run, are dealt to
+// the waves round-robin (step k to wave k mod W).  Every wave thus gets the
+// same share of each clause length, and only a run's last step is partial.
+// Lane l takes record base + l of a step; each load is 64 consecutive
+// records (one 1 KiB read) at a wave-uniform offset plus the lane's fixed
+// one, and the wave's next step is loaded while the current one is
+// processed.
 template <int LEN, bool kSample, bool kClust, int NB>
-__device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int lane,
-                                              const PhiloxSweep &ps, Key2 key, uint32_t nbh, uint32_t full,
-                                              uint32_t lmask) {
+__device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int step0,
+                                              int wave, int nw, int lane, const PhiloxSweep &ps, Key2 key,
+                                              uint32_t nbh, uint32_t full, uint32_t lmask) {
     int cnt = 0;
     if (lo >= hi) return 0;
-    uint4 rn;
-    uint32_t on;
-    rec_load(rv, lo, lane, rn, on);
-    for (int base = lo; base < hi; base += kWave) {
-        const uint4 r = rn;
-        const uint32_t oc = on;
-        if (base + kWave < hi) rec_load(rv, base + kWave, lane, rn, on);
-        if (base + lane < hi) cnt += clause_one<LEN, kSample, kClust, NB>(L, r, oc, ps, key, nbh, full, lmask);
+    const int first = (wave - step0 % nw + nw) % nw;         // this wave's first step of the run
+    const int stride = nw * kWave;
+    int base = lo + first * kWave;
+    if (base >= hi) return 0;
+    // two register sets alternate (no copies): step A is processed while
+    // step B loads, then the other way round
+    uint4 ra, rb;
+    uint32_t oa, ob;
+    rec_load(rv, base, lane, ra, oa);
+    for (;;) {
+        int next = base + stride;
+        if (next < hi) rec_load(rv, next, lane, rb, ob);
+        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB>(L, ra, oa, ps, key, nbh, full, lmask);
+        if (next >= hi) break;
+        base = next;
+        next = base + stride;
+        if (next < hi) rec_load(rv, next, lane, ra, oa);
+        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB>(L, rb, ob, ps, key, nbh, full, lmask);
+        if (next >= hi) break;
+        base = next;
     }
     return cnt;
 }
 
 // Clause phase over the M records of a range (a formula's, or a split
 // member's run), sorted by clause length with bnd[k] = the number of records
-// of length <= k (bnd[0] = 0, bnd[7] = M).  Wave w of the workgroup takes
-// the contiguous chunk [w M / W, (w + 1) M / W) and walks it length by
-// length, so every step of a wave is one clause length (the gather and
-// scatter unrolled for it) with no per-record length test.  Returns this
-// thread's number of satisfied clauses.
+// of length <= k (bnd[0] = 0, bnd[7] = M).  The waves walk the records
+// length by length in steps of 64 dealt round-robin, so every step of a wave
+// is one clause length (the gather and scatter unrolled for it) with no
+// per-record length test.  Returns this thread's number of satisfied
+// clauses.
 template <bool kSample, bool kClust, int NB>
-__device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &rv, int lo, int hi,
-                                               const int32_t (&bnd)[8], int lane, const PhiloxSweep &ps, Key2 key,
-                                               uint32_t nbh, uint32_t full, uint32_t lmask) {
+__device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &rv, const int32_t (&bnd)[8], int wave,
+                                               int nw, int lane, const PhiloxSweep &ps, Key2 key, uint32_t nbh,
+                                               uint32_t full, uint32_t lmask) {
     int cnt = 0;
-#define HP_SEG(LEN)                                                                                                 \
-    cnt += clause_segment<LEN, kSample, kClust, NB>(L, rv, max(lo, bnd[LEN - 1]), min(hi, bnd[LEN]), lane, ps, key, \
-                                                    nbh, full, lmask)
+    int step = 0;                  // steps of the runs of shorter clauses
+#define HP_SEG(LEN)                                                                                                  \
+    cnt += clause_segment<LEN, kSample, kClust, NB>(L, rv, bnd[LEN - 1], bnd[LEN], step, wave, nw, lane, ps, key,    \
+                                                    nbh, full, lmask);                                               \
+    step += (bnd[LEN] - bnd[LEN - 1] + kWave - 1) / kWave
     HP_SEG(1);
     HP_SEG(2);
     HP_SEG(3);
@@ -656,11 +674,10 @@ __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__res
                                             uint32_t full, uint32_t lmask) {
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), nw = NT / kWave;
-    const int lo = (int)((int64_t)wave * M / nw), hi = (int)((int64_t)(wave + 1) * M / nw);
     const RecView rv = rec_view(rec, orig, M);
-    if (kClust) return clause_phase_nb<kSample, kClust, 0>(L, rv, lo, hi, bnd, lane, ps, key, nbh, full, lmask);
-    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2>(L, rv, lo, hi, bnd, lane, ps, key, nbh, full, lmask)
-                   : clause_phase_nb<kSample, kClust, 1>(L, rv, lo, hi, bnd, lane, ps, key, nbh, full, lmask);
+    if (kClust) return clause_phase_nb<kSample, kClust, 0>(L, rv, bnd, wave, nw, lane, ps, key, nbh, full, lmask);
+    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2>(L, rv, bnd, wave, nw, lane, ps, key, nbh, full, lmask)
+                   : clause_phase_nb<kSample, kClust, 1>(L, rv, bnd, wave, nw, lane, ps, key, nbh, full, lmask);
 }
 
 // Range-relative length bounds of split member g of G: the member's run
