@@ -327,8 +327,9 @@ def main(argv=None):
                    kernel=args.kernel, split=args.split, graph=use_graph, size_rbms=w.size_rbms)
     progress(f"planned: {plan.info()['n_buckets']} launch(es)")
     if (args.tune if args.tune >= 0 else int(batch)) == 1:
-        plan.tune(n_sweeps=3)
-        progress(f"tuned: workgroup sizes {plan.info()['bucket_threads']}")
+        plan.tune(n_sweeps=10)
+        progress(f"tuned: workgroup sizes {plan.info()['bucket_threads']}, table layouts "
+                 f"{plan.info()['bucket_kind']}")
     st = plan.new_state(w.v0, device=dev)
     stream = torch.cuda.current_stream()
     for i in range(args.warmup):

@@ -202,9 +202,13 @@ hp_status hp_run(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *
  * their results are undefined; order them on one stream. */
 hp_status hp_run_noalloc(hp_plan_t plan, const hp_state *state, int64_t n_sweeps, void *stream);
 
-/* Autotuner: for every launch of the plan, time each candidate workgroup
- * size (64..1024) on `n_sweeps` sweeps of the given state and keep the
- * fastest.  The trial runs overwrite the state's v, nu, s_max and best
+/* Autotuner: for every launch of the plan, time each candidate shape on
+ * `n_sweeps` sweeps of the given state and keep the fastest.  A shape is a
+ * workgroup size (64..1024) and, for the push kernels of the padded model in
+ * FP64/FP32, the table layout: every table in LDS, the merged padding table
+ * in global memory, or both contribution tables in global memory (smaller
+ * LDS footprints let more workgroups share a CU).  All shapes compute the
+ * same bits.  The trial runs overwrite the state's v, nu, s_max and best
  * without advancing t, so pass a scratch state of the right shape.
  * Synchronous.  Cached graphs are discarded. */
 hp_status hp_tune(hp_plan_t plan, const hp_state *scratch, int64_t n_sweeps, void *stream);

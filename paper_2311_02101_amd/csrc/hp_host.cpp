@@ -511,6 +511,28 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         release(p);
         return fail(HP_EUNSUPPORTED, "too many size classes");
     }
+    // XCD groups inside every bucket: whole formulas (their B chains stay
+    // together), each given to the XCD with the least work so far in the
+    // bucket's largest-first order; the bucket's items are reordered group by
+    // group
+    for (Bucket &bk : p->buckets) {
+        std::vector<std::vector<WorkItem>> grp(kXcds);
+        double load[kXcds] = {};
+        for (int j = bk.first; j < bk.first + bk.count; j += B) {
+            const int f = work[j].f;
+            int x = 0;
+            for (int y = 1; y < kXcds; ++y)
+                if (load[y] < load[x]) x = y;
+            load[x] += 7.0 * fd[f].n + fd[f].c;
+            for (int b = 0; b < B; ++b) grp[x].push_back(work[j + b]);
+        }
+        int pos = bk.first;
+        for (int x = 0; x < kXcds; ++x) {
+            bk.xq[x] = pos - bk.first;
+            for (const WorkItem &wi : grp[x]) work[pos++] = wi;
+        }
+        bk.xq[kXcds] = pos - bk.first;
+    }
     p->n_work = (int32_t)work.size();
     e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) { release(p); return hip_fail(e, "hipDeviceGetAttribute"); }
@@ -675,7 +697,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_err), 1, s), "clear error flag");
     HP_TRY(hipMalloc((void **)&p->d_tabflag, sizeof(int32_t)), "alloc table flag");
     HP_TRY(launch_zero(reinterpret_cast<uint32_t *>(p->d_tabflag), 1, s), "clear table flag");
-    HP_TRY(hipMalloc((void **)&p->d_queue, kMaxBuckets * 32 * sizeof(uint32_t)), "alloc work counters");
+    HP_TRY(hipMalloc((void **)&p->d_queue, kMaxBuckets * kQueueWords * sizeof(uint32_t)), "alloc work counters");
     for (size_t i = 0; i < p->buckets.size() && p->buckets.size() > 1; ++i)
         HP_TRY(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking), "side stream");
     if (p->buckets.size() > 1) {
@@ -793,14 +815,34 @@ hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *st
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     for (Bucket &bk : p->buckets) {
         if (e != hipSuccess) break;
         const Bucket orig = bk;
         float best_ms = -1.0f;
         Bucket best = bk;
+        // the candidate shapes: the table layout of the push kernel (every
+        // table in LDS; the padding table in global memory; both contribution
+        // tables in global memory -- a smaller LDS footprint lets more
+        // workgroups share a CU) and the workgroup size
+        std::vector<int> kinds{orig.kind};
+        const bool layouts = orig.kind != kBucketPull && !p->clust && p->precision != HP_MIXED_BF16;
+        if (layouts) {
+            kinds.clear();
+            for (int k : {(int)kBucketPush, (int)kBucketMid, (int)kBucketWide}) {
+                int32_t vo, xo;
+                if (lds_bytes_push(orig.max_n, k, &vo, &xo) <= (size_t)max_lds) kinds.push_back(k);
+            }
+        }
+        for (size_t ki = 0; ki < kinds.size() && e == hipSuccess; ++ki)
         for (int t = 64; t <= kMaxThreads && e == hipSuccess; t *= 2) {
             bk = orig;
             bk.threads = t;
+            if (layouts) {
+                bk.kind = kinds[ki];
+                bk.lds = lds_bytes_push(bk.max_n, bk.kind, &bk.v_off, &bk.x_off);
+            }
             const int groups = (bk.max_n + 3) / 4;
             bk.vpt = vpt_for(groups, t, p->precision == HP_MIXED_BF16, p->precision != HP_FP32);
             const int occ = bucket_occupancy(*p, bk);

@@ -156,6 +156,21 @@ enum class Variant { kPull = 0, kPush = 1 };
 // push: every table in LDS; mid: the merged padding table gpad read from
 // global memory (one read per clause), the rest in LDS; wide: both
 // contribution tables in global memory (the largest formulas)
+// XCDs of the GPU (MI355X: 8 compute dies, each with its own L2); workgroup
+// w of a launch is dispatched to XCD w mod 8
+constexpr int kXcds = 8;
+// work counters of one launch: one per XCD, each on its own 128-byte line
+constexpr int kQueueWords = kXcds * 32;
+
+// Work queue of a persistent launch: ctr == nullptr runs item w on
+// workgroup w; else workgroups take items of their own XCD's range first,
+// then help the other XCDs' ranges.
+struct WorkQueue {
+    uint32_t *ctr;               // [kXcds][32] counters, zeroed before the launch
+    int32_t count;               // items of the launch
+    int32_t xq[kXcds + 1];       // item ranges per XCD
+};
+
 enum BucketKind : int32_t { kBucketPush = 0, kBucketWide = 1, kBucketPull = 2, kBucketMid = 3 };
 constexpr int kMaxBuckets = 32;
 
@@ -167,6 +182,9 @@ struct Bucket {
     size_t lds = 0;
     int32_t v_off = 0, x_off = 0, hm_off = 0;
     int32_t grid = 0;               // persistent grid (0: one workgroup per item)
+    // persistent grids: the items are grouped by XCD, [xq[x], xq[x+1]) for
+    // XCD x (offsets from `first`); whole formulas per XCD, balanced by work
+    int32_t xq[kXcds + 1] = {};
 };
 
 struct GraphEntry {
@@ -201,7 +219,7 @@ struct Plan {
     hipEvent_t ev_join[kMaxBuckets] = {};
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
-    uint32_t *d_queue = nullptr;     // [kMaxBuckets * 32] persistent work counters
+    uint32_t *d_queue = nullptr;     // [kMaxBuckets][kQueueWords] persistent work counters
     int64_t *d_var_off = nullptr;    // [F+1]
     int64_t *d_clause_off = nullptr; // [F+1]
     float *d_feat_acc = nullptr;     // feature workspace, allocated on first use
@@ -238,7 +256,7 @@ struct Plan {
 // uses the plan's own; hp_run_noalloc carves them out of the library's static
 // scratch array (kScratchBytes per device).
 struct RunBuffers {
-    uint32_t *queue;             // [kMaxBuckets][32] work counters (one 128-byte line each)
+    uint32_t *queue;             // [kMaxBuckets][kQueueWords] work counters
     int64_t *xpart;              // split: [items][G][nstride] partial logits
     uint8_t *vbuf;               // split: [items][nstride] packed new values
     int32_t *cnt;                // split: [items][2][kMaxSplit] partial counts

@@ -849,12 +849,16 @@ __device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, i
     return total;
 }
 
-// One chain per workgroup at a time.  queue == nullptr: workgroup w runs
-// item w.  Otherwise the grid is persistent: workgroups take items from an
-// atomic counter (zeroed before the launch) until all `count` items are done,
-// largest formulas first, so uneven sizes balance over the resident grid.
+// One chain per workgroup at a time.  Q.ctr == nullptr: workgroup w runs
+// item w.  Otherwise the grid is persistent: workgroups take items from
+// atomic counters (zeroed before the launch), largest formulas first, so
+// uneven sizes balance over the resident grid.  The items are grouped by
+// XCD (whole formulas, balanced by work): a workgroup drains its own XCD's
+// range first, so the workgroups that share an L2 run the chains of the same
+// few formulas and their clause records stay in that L2, then it helps the
+// other ranges in turn.
 template <typename Real, int VPT, int kTab, bool kMfma = false, bool kClust = false>
-__global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, uint32_t *queue, int count) {
+__global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, WorkQueue Q) {
     extern __shared__ __align__(16) unsigned char lds[];
     int *s_item = reinterpret_cast<int *>(lds + (kClust                  ? kClustCntOff
                                                  : kTab == kBucketWide ? kWideCntOff
@@ -871,17 +875,32 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, u
     const double fx_scale = P.fx_scale;
     const int64_t t0 = *P.t_ptr;
 
+    const int home = (int)(blockIdx.x % kXcds);
+    int qx = 0;                       // thread 0: ranges drained so far (own XCD first)
     for (int it = 0;; ++it) {
         int item;
-        if (queue == nullptr) {
+        if (Q.ctr == nullptr) {
             if (it > 0) break;
             item = blockIdx.x;
         } else {
-            if (tid == 0) *s_item = (int)atomicAdd(queue, 1u);
+            if (tid == 0) {
+                int got = -1;
+                for (; qx < kXcds; ++qx) {
+                    const int x = (home + qx) % kXcds;
+                    const int n = Q.xq[x + 1] - Q.xq[x];
+                    if (n <= 0) continue;
+                    const uint32_t k = atomicAdd(Q.ctr + 32 * x, 1u);
+                    if (k < (uint32_t)n) {
+                        got = Q.xq[x] + (int)k;
+                        break;
+                    }
+                }
+                *s_item = got;
+            }
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(*s_item);    // the same for every thread
             __syncthreads();          // s_item is rewritten by the next take
-            if (item >= count) break;
+            if (item < 0) break;
         }
         const WorkItem w = P.work[item];
         const FormulaDev fd = P.fd[w.f];
@@ -1547,7 +1566,7 @@ static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 static void scratch_layout(const Plan &p, size_t off[4], size_t *total) {
     const size_t items = p.split > 1 ? (size_t)p.buckets[0].count : 0;
     off[0] = 0;
-    off[1] = align256(off[0] + (size_t)kMaxBuckets * 32 * sizeof(uint32_t));
+    off[1] = align256(off[0] + (size_t)kMaxBuckets * kQueueWords * sizeof(uint32_t));
     off[2] = align256(off[1] + items * p.split * p.nstride * sizeof(int64_t));
     off[3] = align256(off[2] + items * p.nstride);
     *total = align256(off[3] + items * 2 * kMaxSplit * sizeof(int32_t));
@@ -1582,20 +1601,22 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
                            b.lds, s, P);
         return hipGetLastError();
     }
-    uint32_t *queue = nullptr;
+    WorkQueue Q;
+    Q.ctr = nullptr;
+    Q.count = b.count;
+    for (int x = 0; x <= kXcds; ++x) Q.xq[x] = b.xq[x];
     int grid = b.count;
     if (b.grid > 0) {
-        // the bucket's work counter sits on its own 128-byte line
-        queue = queues + 32 * (size_t)(&b - p.buckets.data());
-        hipError_t e = launch_zero(queue, 1, s);
+        // the bucket's counters: one 128-byte line per XCD
+        Q.ctr = queues + kQueueWords * (size_t)(&b - p.buckets.data());
+        hipError_t e = launch_zero(Q.ctr, kQueueWords, s);
         if (e != hipSuccess) return e;
         grid = b.grid;
     }
     const void *kern = p.precision == HP_MIXED_BF16 ? mixed_kernel_ptr(b.vpt)
                        : p.clust                     ? clust_kernel_ptr<Real>(b.vpt)
                                                      : push_kernel_ptr<Real>(b.vpt, b.kind);
-    hipLaunchKernelGGL((void (*)(SweepParams<Real>, uint32_t *, int))kern, dim3(grid), dim3(b.threads), b.lds, s, P,
-                       queue, b.count);
+    hipLaunchKernelGGL((void (*)(SweepParams<Real>, WorkQueue))kern, dim3(grid), dim3(b.threads), b.lds, s, P, Q);
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ def test_uneven_1024x64_fp32_graph_tuned_sampled_formulas(hip, uneven_workload):
     say("[uneven 1024x64] plan: FP32, graph, then tune")
     plan = hp.Plan(w.tables, w.n_vars, w.W, w.b, chains=w.chains, temps=w.temps, precision="f32",
                    alpha=w.alpha, seed=w.seed, graph=True)
-    plan.tune(n_sweeps=3)
+    plan.tune(n_sweeps=10)
     info = plan.info()
     say(f"[uneven 1024x64] {info['n_buckets']} launches, threads {info['bucket_threads'][:info['n_buckets']]}")
     assert info["n_buckets"] > 1 and info["split"] == 1
