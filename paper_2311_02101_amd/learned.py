@@ -13,6 +13,7 @@ backward, Adam, initial draws, label reduction); this module only allocates
 buffers and drives the loop.
 
     python -m paper_2311_02101_amd.learned --instances 100000   # full-size training run
+    python -m paper_2311_02101_amd.learned --mlp-bench 4194304  # MLP kernels alone (JSON)
 """
 from __future__ import annotations
 
@@ -277,8 +278,47 @@ def evaluate(net, n_formulas, n_vars=2048, seed=4, chains=64, sweeps=(20, 100, 5
     return out
 
 
+def mlp_bench(rows, rounds=5, seed=4):
+    """Time the MLP kernels alone on `rows` random feature rows: forward, and
+    forward + backward (one fused kernel) + Adam, `rounds` times each after a
+    warm-up.  Algorithmic work per row: the forward product 2 * 32 * 256 and
+    the output 2 * 256 flops; the backward recomputes the forward and adds
+    dh = w2 * relu'(h) (256), dW1 = x^T dh (2 * 32 * 256) and dw2 (2 * 256).
+    Bytes per row: 64 of bfloat16 features, 4 of label, 4 of output."""
+    import torch
+    net = MLP(seed=seed)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    feat = torch.rand(rows, F_IN, generator=gen).to("cuda")
+    x = feat.to(torch.bfloat16).view(torch.int16)
+    y = torch.rand(rows, generator=gen).to("cuda")
+    q = torch.empty(rows, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(rounds):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / rounds
+
+    t_fwd = timed(lambda: net.forward(x, q))
+    t_bwd = timed(lambda: (net.backward(x, y), net.adam()))
+    fwd_flops = rows * (2 * F_IN * HIDDEN + 2 * HIDDEN)
+    bwd_flops = rows * (2 * F_IN * HIDDEN + 2 * HIDDEN + HIDDEN + 2 * F_IN * HIDDEN + 2 * HIDDEN)
+    return {"rows": rows, "forward_s": t_fwd, "forward_rows_per_s": rows / t_fwd,
+            "forward_tflops": fwd_flops / t_fwd / 1e12, "forward_hbm_gbs": rows * (64 + 4) / t_fwd / 1e9,
+            "train_step_s": t_bwd, "train_rows_per_s": rows / t_bwd, "train_tflops": bwd_flops / t_bwd / 1e12,
+            "train_hbm_gbs": rows * (64 + 4) / t_bwd / 1e9, "mfma_bf16_peak_tflops": 2500.0}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mlp-bench", type=int, default=0,
+                    help="only time the MLP kernels on this many random feature rows and print JSON")
     ap.add_argument("--instances", type=int, default=100000)
     ap.add_argument("--n-vars", type=int, default=2048)
     ap.add_argument("--label-sweeps", type=int, default=500)
@@ -288,6 +328,9 @@ def main(argv=None):
     ap.add_argument("--out", default=WEIGHTS_JSON)
     ap.add_argument("--workers", type=int, default=16, help="host processes generating formulas")
     args = ap.parse_args(argv)
+    if args.mlp_bench > 0:
+        print(json.dumps(mlp_bench(args.mlp_bench)), flush=True)
+        return 0
     pool = FormulaPool(args.workers)      # forked before the GPU is used
 
     def log(msg):

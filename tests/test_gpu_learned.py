@@ -144,6 +144,39 @@ def test_learned_initializer_trains_and_is_judged_by_the_count(hip):
     ev = Lr.evaluate(net, 16, n_vars=512, seed=21, chains=32, sweeps=(10, 50))
     say(f"[learned] evaluation {ev}")
     for s, r in ev.items():
-        # the answer is the better half, so the plain method bounds it below
-        assert max(r["mlp"], r["uniform"]) >= r["uniform"]
-        assert r["wins"] + r["losses"] <= 16
+        # paired per formula: the plain method is the fallback wherever the
+        # uniform half is better
+        assert r["wins"] + r["losses"] <= 16 and r["fallback_used"] == r["losses"]
+
+
+def test_trained_network_gains_over_uniform_starts(hip):
+    """The committed network (trained on 1e5 method-labelled formulas of
+    N = 2048) on 32 held-out formulas it never saw: its predictions beat the
+    best constant predictor on fresh labels, and the chains it starts beat
+    the uniform starts of the same formulas (paired, same temperatures) at
+    20 and 100 sweeps."""
+    import torch
+    from paper_2311_02101_amd import learned as Lr
+    net, _ = Lr.MLP.load()
+    first = 2 * 10 ** 6                   # held out: training used 0 .. 1e5, the stored evaluation 1e6 ..
+    say("[learned gain] labels of 16 held-out formulas N=2048 (32 chains x 500 sweeps)")
+    x, y = Lr.make_dataset(16, n_vars=2048, seed=4, chains=32, sweeps=500, batch=16, first=first)
+    q = net.forward(x).double()
+    yd = y.double()
+    eps = 1e-7
+
+    def bce(p):
+        p = p.clamp(eps, 1 - eps)
+        return float(-(yd * torch.log(p) + (1 - yd) * torch.log(1 - p)).mean())
+    loss_net, loss_const = bce(q), bce(torch.full_like(yd, float(yd.mean())))
+    say(f"[learned gain] held-out loss {loss_net:.5f} vs constant predictor {loss_const:.5f}")
+    assert loss_net < loss_const - 0.005
+    say("[learned gain] 32 held-out formulas, 64 chains (32 MLP-started, 32 uniform)")
+    ev = Lr.evaluate(net, 32, n_vars=2048, seed=4, chains=64, sweeps=(20, 100), first=first + 1000)
+    for s, r in ev.items():
+        say(f"[learned gain] {s} sweeps: MLP half {r['mlp']:.1f}, uniform half {r['uniform']:.1f}, "
+            f"gain {r['gain']:+.1f} clauses of {r['clauses']}, wins {r['wins']} / losses {r['losses']}")
+    # margins: a third of the gain measured on 256 formulas (+124 at 20 sweeps),
+    # and a clear majority of paired wins
+    assert ev[20]["gain"] >= 40 and ev[20]["wins"] >= 28
+    assert ev[100]["gain"] > 0 and ev[100]["wins"] > ev[100]["losses"]
