@@ -276,6 +276,9 @@ def main(argv=None):
     ap.add_argument("--tune", type=int, default=-1, help="autotune first (default: on for batches)")
     ap.add_argument("--model", default="padded", choices=["padded", "clustered"],
                     help="padded formula-RBM (K = 7, L = 8 for every clause) or the size-clustered one")
+    ap.add_argument("--philox-probe", type=int, default=0,
+                    help="only time the sweep generator alone (hp_philox_xor) on this many M Philox blocks "
+                         "and report VALU lane-slots per block at the rated clock, then exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run y = -x over this many MiB (a plain streaming kernel whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters), then exit")
@@ -288,6 +291,30 @@ def main(argv=None):
 
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.philox_probe > 0:
+        # every SIMD lane of the chip busy: 256 CUs x 4 SIMDs x 64 lanes x 8 waves
+        import torch
+        from paper_2311_02101_amd import hp
+        n_out = 256 * 4 * 64 * 8
+        blocks = max(1, args.philox_probe * (1 << 20) // n_out)
+        out = torch.empty(n_out, dtype=torch.int32, device="cuda")
+        hp.philox_xor(1, 0, 0, 0, 0, blocks, n_out, out)         # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for rep in range(3):
+            hp.philox_xor(1, 0, rep, 0, 0, blocks, n_out, out)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / 3
+        calls = n_out * blocks
+        print(json.dumps({"philox_blocks": calls, "seconds": sec, "blocks_per_s": calls / sec,
+                          "lane_slots_per_block": PEAK_SLOTS * sec / calls,
+                          "model_slots_per_block": PHILOX_SLOTS,
+                          "note": "two interleaved blocks per step, first two rounds from per-sweep constants, "
+                                  "plus about 3 XORs per block to reduce the words"}), flush=True)
+        return 0
 
     if args.copy_probe_mib > 0:
         import torch

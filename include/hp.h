@@ -244,6 +244,19 @@ hp_status hp_check(hp_plan_t plan);
  * accepted. */
 hp_status hp_free(hp_plan_t plan);
 
+/* Checksum of the sweeps' random stream, for comparing the generator of two
+ * builds and for timing it alone.  out[j] (j < n_out) is the XOR of all four
+ * words of Philox4x32-10 (Salmon et al., SC'11) over the blocks
+ * i = j * blocks .. (j + 1) * blocks - 1 at counter (t mod 2^32, chain,
+ * phase * 2^31 + i, t div 2^32) with key (seed mod 2^32, (seed div 2^32) xor
+ * formula) -- the counters and key a sweep of that chain uses, evaluated in
+ * the sweep kernels' form (the first two rounds from per-sweep constants, two
+ * blocks interleaved).  out: DEVICE [n_out] uint32.  HP_EINVAL unless
+ * phase is 0 or 1, blocks >= 1, n_out >= 1 and (n_out * blocks) <= 2^31.
+ * Stream-ordered. */
+hp_status hp_philox_xor(uint64_t seed, int32_t formula, int64_t t, int32_t chain, int32_t phase, int64_t blocks,
+                        int64_t n_out, uint32_t *out, void *stream);
+
 /* Static description of a status code. */
 const char *hp_status_string(hp_status s);
 

@@ -1029,6 +1029,18 @@ hp_status hp_chain_mean(hp_plan_t plan, const uint8_t *a, float *out, void *stre
     return HP_OK;
 }
 
+hp_status hp_philox_xor(uint64_t seed, int32_t formula, int64_t t, int32_t chain, int32_t phase, int64_t blocks,
+                        int64_t n_out, uint32_t *out, void *stream) {
+    g_last_error.clear();
+    if (!out) return fail(HP_EINVAL, "null output");
+    if (phase != 0 && phase != 1) return fail(HP_EINVAL, "phase must be 0 (hidden) or 1 (visible)");
+    if (blocks < 1 || n_out < 1 || n_out > (int64_t(1) << 31) / blocks)
+        return fail(HP_EINVAL, "need blocks >= 1, n_out >= 1 and n_out * blocks <= 2^31");
+    hipError_t e = launch_philox_xor(seed, formula, t, chain, phase, blocks, n_out, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "philox kernel");
+    return HP_OK;
+}
+
 hp_status hp_free(hp_plan_t plan) {
     g_last_error.clear();
     Plan *p = reinterpret_cast<Plan *>(plan);

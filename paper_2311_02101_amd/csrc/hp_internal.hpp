@@ -284,6 +284,8 @@ hipError_t set_kernel_lds_limits(int bytes);
 int bucket_occupancy(const Plan &p, const Bucket &b);
 
 hipError_t launch_zero(uint32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_philox_xor(uint64_t seed, int32_t formula, int64_t t, int32_t chain, int32_t phase, int64_t blocks,
+                             int64_t n_out, uint32_t *out, hipStream_t s);
 
 // owned variables per thread of a split member (1 or 2 in registers, else
 // 0) for the largest formula, G members and the given workgroup size

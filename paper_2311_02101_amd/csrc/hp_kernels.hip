@@ -1351,6 +1351,39 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     if (g == 0 && tid == 0) P.s_max[(int64_t)w.f * P.B + w.b] = smax;
 }
 
+// XOR of the Philox blocks [j * blocks, (j + 1) * blocks) of one sweep's
+// stream, in the sweep kernels' form (two interleaved blocks per step).
+__global__ void philox_xor_kernel(uint32_t key0, uint32_t key1, uint64_t t, uint32_t chain, uint32_t phase,
+                                  int64_t blocks, int64_t n_out, uint32_t *__restrict__ out) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_out) return;
+    const Key2 key{key0, key1};
+    const PhiloxSweep ps = philox_sweep_consts((uint32_t)t, chain, (uint32_t)(t >> 32), key);
+    const uint32_t first = (uint32_t)(j * blocks), ph = phase ? kPhaseVisible : kPhaseHidden;
+    uint32_t acc = 0;
+    int64_t i = 0;
+    for (; i + 1 < blocks; i += 2) {
+        uint4 r[2];
+        const uint32_t w[2] = {ph | (first + (uint32_t)i), ph | (first + (uint32_t)i + 1u)};
+        philox_sweep_multi<2>(r, w, ps, key);
+        acc ^= r[0].x ^ r[0].y ^ r[0].z ^ r[0].w ^ r[1].x ^ r[1].y ^ r[1].z ^ r[1].w;
+    }
+    if (i < blocks) {
+        const uint4 r = philox_sweep(ph | (first + (uint32_t)i), ps, key);
+        acc ^= r.x ^ r.y ^ r.z ^ r.w;
+    }
+    out[j] = acc;
+}
+
+hipError_t launch_philox_xor(uint64_t seed, int32_t formula, int64_t t, int32_t chain, int32_t phase, int64_t blocks,
+                             int64_t n_out, uint32_t *out, hipStream_t s) {
+    const int64_t grid = (n_out + 255) / 256;
+    philox_xor_kernel<<<(unsigned)grid, 256, 0, s>>>((uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)formula,
+                                                     (uint64_t)t, (uint32_t)chain, (uint32_t)phase, blocks, n_out,
+                                                     out);
+    return hipGetLastError();
+}
+
 __global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;

@@ -22,7 +22,7 @@ KERNEL = {"auto": 0, "pull": 1, "push": 2}
 
 EXPORTS = ("hp_plan", "hp_run", "hp_run_noalloc", "hp_tune", "hp_check", "hp_plan_query", "hp_free",
            "hp_status_string", "hp_last_error", "hp_unit_propagate", "hp_merge_candidates", "hp_temper",
-           "hp_get_temps")
+           "hp_get_temps", "hp_philox_xor")
 
 
 class HpError(RuntimeError):
@@ -109,6 +109,9 @@ def load():
     lib.hp_temper.restype = ct.c_int
     lib.hp_get_temps.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
     lib.hp_get_temps.restype = ct.c_int
+    lib.hp_philox_xor.argtypes = [ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int64,
+                                  ct.c_int64, ct.c_void_p, ct.c_void_p]
+    lib.hp_philox_xor.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -133,6 +136,12 @@ def unit_propagate(tables, n_vars, formula, v, nu, threads=0):
     _check(lib.hp_unit_propagate(ct.byref(cnf), int(formula), v.shape[0], v.ctypes.data, nu.ctypes.data,
                                  out.ctypes.data, int(threads)))
     return out
+
+
+def philox_xor(seed, formula, t, chain, phase, blocks, n_out, out, stream=None):
+    """hp_philox_xor into the device uint32 tensor `out` ([n_out])."""
+    _check(load().hp_philox_xor(int(seed) & (2 ** 64 - 1), int(formula), int(t), int(chain), int(phase),
+                                int(blocks), int(n_out), ct.c_void_p(out.data_ptr()), _stream_handle(stream)))
 
 
 def device_available() -> bool:

@@ -1,0 +1,63 @@
+"""Property-based GPU parity on tiny random formulas (Hypothesis, derandomized):
+for any formula of 1..40 variables and 1..80 clauses of width 1..7, random
+N(0,1) OR-gate weights, 1..6 chains over two temperatures and 0..8 sweeps,
+the HIP path (push or pull kernel, FP64) ends in the oracle's state: v,
+s_max and best exactly, nu within the FP64 class (a differing visible draw
+must be a tie of the plan's bound, replayed with teacher forcing).
+
+Every example prints its sizes and seed before touching the GPU."""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+from oracle import rbmsat as R
+from paper_2311_02101_amd import workload as wl
+from tests.parity import compare_state, f64_bounds, say, teacher_forced_sweep
+
+pytestmark = pytest.mark.gpu
+
+
+@st.composite
+def formulas(draw):
+    n = draw(st.integers(1, 40))
+    k = draw(st.integers(1, 7))
+    c = draw(st.integers(1, 80))
+    clauses = []
+    for _ in range(c):
+        ln = draw(st.integers(1, k))
+        lits = draw(st.lists(st.integers(1, n), min_size=ln, max_size=ln))
+        signs = draw(st.lists(st.sampled_from([1, -1]), min_size=ln, max_size=ln))
+        clauses.append([s * v for s, v in zip(signs, lits)])
+    return n, k, clauses
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+@given(formulas(), st.integers(0, 2 ** 31 - 1), st.integers(1, 6), st.integers(0, 8),
+       st.sampled_from(["push", "pull"]))
+def test_random_tiny_formulas_match_oracle(hip, f, seed, chains, sweeps, kernel):
+    from paper_2311_02101_amd import hp
+    n, k, clauses = f
+    T = wl.pad_clauses(clauses, k)
+    L = 3 if k <= 3 else k + 1
+    rng = np.random.default_rng(seed)
+    W, b = rng.standard_normal((2, k, L)), rng.standard_normal((2, L))
+    temps = wl.default_temperatures(chains, 2)
+    say(f"[property] N={n} C={len(clauses)} K={k} L={L} B={chains} S={sweeps} {kernel} seed={seed}")
+    plan = hp.Plan([T], [n], W, b, chains=chains, temps=temps, precision="f64", seed=seed, kernel=kernel)
+    tie, nu_rtol = f64_bounds(plan, [T])
+    v0 = wl.initial_state(chains, n, seed % 1000)
+    st_ = plan.new_state([v0])
+    plan.run(st_, sweeps)
+    op = R.plan(T, n, W, b)
+    ost = R.run(R.initial(v0), op, temps, sweeps, alpha=1e-3, seed=seed)
+    try:
+        compare_state(st_.formula(0), (ost.v, ost.nu, ost.s_max, ost.best), "f64", "property", nu_rtol=nu_rtol)
+    except AssertionError:
+        # every differing draw must be a tie: replay sweep by sweep
+        s2 = plan.new_state([v0])
+        o2 = R.initial(v0)
+        ties = sum(teacher_forced_sweep(plan, s2, 0, o2, op, temps, alpha=1e-3, seed=seed, prec="f64",
+                                        tie=tie, nu_rtol=nu_rtol) for _ in range(sweeps))
+        assert ties > 0
+    plan.free()

@@ -31,10 +31,17 @@ def _check_round(plan, st, tables, sizes, W, b, parity, seed):
         F = PT.clause_free_energies(tables[f], n, W, b, v)
         rec = []
         want = PT.swap_round(temps0[f], F, parity, t, seed, f, rec)
-        close = [r for r in rec if abs(r[3] - np.exp(min(r[2], 0.0))) < TIE]
-        ties += len(close)
-        if not close:
-            assert np.array_equal(got[f], want), (f, rec)
+        # the pairs of a round are disjoint: a near-tie acceptance draw leaves
+        # only its own two chains undecided (either outcome is correct there,
+        # as long as the pair keeps its two temperatures); every other chain
+        # is compared exactly
+        undecided = np.zeros(len(want), bool)
+        for a, bb, D, u, _ in rec:
+            if abs(u - np.exp(min(D, 0.0))) < TIE:
+                undecided[[a, bb]] = True
+                assert sorted((got[f][a], got[f][bb])) == sorted((temps0[f][a], temps0[f][bb])), (f, a, bb)
+                ties += 1
+        assert np.array_equal(got[f][~undecided], want[~undecided]), (f, rec)
     return ties
 
 
