@@ -222,10 +222,13 @@ typedef struct {
     int32_t fx_shift;               /* S: push accumulators count units of 2^-S       */
     int32_t n_buckets;              /* launches per run (one per size class/variant)  */
     int64_t lds_push, lds_pull;     /* largest dynamic LDS bytes per workgroup        */
-    /* first 16 launches: variant (0 push, 1 push with global tables, 2 pull),
-     * work items, workgroup size, largest N, persistent grid (0 = one
-     * workgroup per item) */
+    /* first 16 launches: variant (0 push, 1 push with both contribution
+     * tables in global memory, 2 pull, 3 push with the padding table in
+     * global memory), work items, workgroup size, largest N, persistent grid
+     * (0 = one workgroup per item), clause-phase steps taken from a counter
+     * (1) or dealt round-robin (0) */
     int32_t bucket_kind[16], bucket_items[16], bucket_threads[16], bucket_max_n[16], bucket_grid[16];
+    int32_t bucket_dyn[16];
 } hp_plan_info;
 
 /* Fill *out with the plan's launch configuration.  HP_EINVAL on NULL. */

@@ -131,6 +131,7 @@ struct SweepParams {
     int32_t lds_v_off;           // byte offsets inside dynamic LDS
     int32_t lds_hm_off;          // pull: hidden masks
     int32_t lds_x_off;           // push: int64 accumulators
+    int32_t dyn_steps;           // clause phase: 1 = steps from a workgroup counter, 0 = round-robin
 };
 
 // Split launch: the G workgroups of one chain exchange, every sweep, their
@@ -182,6 +183,7 @@ struct Bucket {
     size_t lds = 0;
     int32_t v_off = 0, x_off = 0, hm_off = 0;
     int32_t grid = 0;               // persistent grid (0: one workgroup per item)
+    int32_t dyn = 1;                // clause-phase steps from a counter (1) or round-robin (0)
     // persistent grids: the items are grouped by XCD, [xq[x], xq[x+1]) for
     // XCD x (offsets from `first`); whole formulas per XCD, balanced by work
     int32_t xq[kXcds + 1] = {};

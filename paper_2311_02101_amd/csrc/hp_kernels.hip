@@ -600,62 +600,92 @@ __device__ __forceinline__ void rec_load(const RecView &rv, int first, int lane,
     oc = __builtin_amdgcn_raw_buffer_load_b32(rv.orig, lane * 4, first * 4, 0);
 }
 
-// The steps of one clause length's run [lo, hi) that fall to this wave:
-// the run is cut into steps of 64 consecutive records, and the steps of all
-// the runs, numbered consecutively from `step0` for this run, are dealt to
-// the waves round-robin (step k to wave k mod W).  Every wave thus gets the
-// same share of each clause length, and only a run's last step is partial.
-// Lane l takes record base + l of a step; each load is 64 consecutive
-// records (one 1 KiB read) at a wave-uniform offset plus the lane's fixed
-// one, and the wave's next step is loaded while the current one is
-// processed.
+// Steps of 64 consecutive records, taken by the waves from a workgroup-wide
+// counter in LDS.  The runs of the clause lengths are cut into steps and
+// numbered in order (run of length 1 first); a wave takes the next step
+// number whenever it starts one, so the waves that the SIMDs serve first
+// simply take more steps and all of them reach the end of the clause phase
+// together (fixed shares left the youngest waves running alone at the end of
+// every clause phase).  The accumulators are exact integers, so which wave
+// takes which step does not change any result.  The counter runs on across
+// the sweeps of an item: every wave takes exactly one step number past the
+// last one per sweep, so sweep s of an item owns the numbers
+// [s (T + W), (s + 1) (T + W)) for T steps and W waves.
+// With dyn == 0 the steps are dealt round-robin instead (step k to wave
+// k mod W, no counter): better when another workgroup shares the CU and
+// fills the SIMDs while this one waits at its barrier.
+struct StepCounter {
+    int *ctr;                    // LDS word, zeroed before the item's first sweep
+    int base;                    // first number of this sweep
+    int dyn;                     // 1: take steps from the counter; 0: round-robin
+    int wave, nw;
+};
+
+__device__ __forceinline__ int take_step(const StepCounter &sc, int lane, int prev) {
+    if (!sc.dyn) return prev < 0 ? sc.wave : prev + sc.nw;
+    int k = 0;
+    if (lane == 0) k = atomicAdd(sc.ctr, 1);
+    return __builtin_amdgcn_readfirstlane(k) - sc.base;
+}
+
+// The steps [olo, ohi) of the run [lo, hi) of clauses of length LEN.  `k`
+// is the wave's current step number: if it is in this run, the wave
+// processes it and keeps taking steps until it gets one past the run, which
+// it leaves in `k` for the next run.  The next step's records are loaded
+// while the current ones are processed (two register sets, no copies).
 template <int LEN, bool kSample, bool kClust, int NB>
-__device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int step0,
-                                              int wave, int nw, int lane, const PhiloxSweep &ps, Key2 key,
-                                              uint32_t nbh, uint32_t full, uint32_t lmask) {
+__device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int olo, int ohi,
+                                              int &k, const StepCounter &sc, int lane, const PhiloxSweep &ps,
+                                              Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
     int cnt = 0;
-    if (lo >= hi) return 0;
-    const int first = (wave - step0 % nw + nw) % nw;         // this wave's first step of the run
-    const int stride = nw * kWave;
-    int base = lo + first * kWave;
-    if (base >= hi) return 0;
-    // two register sets alternate (no copies): step A is processed while
-    // step B loads, then the other way round
+    if (k >= ohi) return 0;
+    int base = lo + (k - olo) * kWave;
     uint4 ra, rb;
     uint32_t oa, ob;
     rec_load(rv, base, lane, ra, oa);
     for (;;) {
-        int next = base + stride;
-        if (next < hi) rec_load(rv, next, lane, rb, ob);
+        int kn = take_step(sc, lane, k);
+        int next = lo + (kn - olo) * kWave;
+        if (kn < ohi) rec_load(rv, next, lane, rb, ob);
         if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB>(L, ra, oa, ps, key, nbh, full, lmask);
-        if (next >= hi) break;
+        k = kn;
+        if (kn >= ohi) break;
         base = next;
-        next = base + stride;
-        if (next < hi) rec_load(rv, next, lane, ra, oa);
+        kn = take_step(sc, lane, k);
+        next = lo + (kn - olo) * kWave;
+        if (kn < ohi) rec_load(rv, next, lane, ra, oa);
         if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB>(L, rb, ob, ps, key, nbh, full, lmask);
-        if (next >= hi) break;
+        k = kn;
+        if (kn >= ohi) break;
         base = next;
     }
     return cnt;
 }
 
+// steps of the runs of a range: o[k] = steps of the runs of lengths < k + 1
+__device__ __forceinline__ void run_steps(const int32_t (&bnd)[8], int32_t (&o)[8]) {
+    o[0] = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) o[k] = o[k - 1] + (bnd[k] - bnd[k - 1] + kWave - 1) / kWave;
+}
+
 // Clause phase over the M records of a range (a formula's, or a split
 // member's run), sorted by clause length with bnd[k] = the number of records
 // of length <= k (bnd[0] = 0, bnd[7] = M).  The waves walk the records
-// length by length in steps of 64 dealt round-robin, so every step of a wave
-// is one clause length (the gather and scatter unrolled for it) with no
-// per-record length test.  Returns this thread's number of satisfied
-// clauses.
+// length by length in steps of 64 (above), so every step is one clause
+// length (the gather and scatter unrolled for it) with no per-record length
+// test.  Returns this thread's number of satisfied clauses.
 template <bool kSample, bool kClust, int NB>
-__device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &rv, const int32_t (&bnd)[8], int wave,
-                                               int nw, int lane, const PhiloxSweep &ps, Key2 key, uint32_t nbh,
-                                               uint32_t full, uint32_t lmask) {
+__device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &rv, const int32_t (&bnd)[8],
+                                               const StepCounter &sc, int lane, const PhiloxSweep &ps, Key2 key,
+                                               uint32_t nbh, uint32_t full, uint32_t lmask) {
+    int32_t o[8];
+    run_steps(bnd, o);
     int cnt = 0;
-    int step = 0;                  // steps of the runs of shorter clauses
-#define HP_SEG(LEN)                                                                                                  \
-    cnt += clause_segment<LEN, kSample, kClust, NB>(L, rv, bnd[LEN - 1], bnd[LEN], step, wave, nw, lane, ps, key,    \
-                                                    nbh, full, lmask);                                               \
-    step += (bnd[LEN] - bnd[LEN - 1] + kWave - 1) / kWave
+    int k = take_step(sc, lane, -1);
+#define HP_SEG(LEN)                                                                                              \
+    cnt += clause_segment<LEN, kSample, kClust, NB>(L, rv, bnd[LEN - 1], bnd[LEN], o[LEN - 1], o[LEN], k, sc,    \
+                                                    lane, ps, key, nbh, full, lmask)
     HP_SEG(1);
     HP_SEG(2);
     HP_SEG(3);
@@ -667,17 +697,23 @@ __device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &
     return cnt;
 }
 
+// step numbers one sweep of a range consumes: T steps plus one per wave
+__device__ __forceinline__ int sweep_step_numbers(const int32_t (&bnd)[8], int NT) {
+    int32_t o[8];
+    run_steps(bnd, o);
+    return o[7] + NT / kWave;
+}
+
 template <bool kSample, bool kClust>
 __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
                                             const uint32_t *__restrict__ orig, int M, const int32_t (&bnd)[8],
-                                            int tid, int NT, const PhiloxSweep &ps, Key2 key, uint32_t nbh,
-                                            uint32_t full, uint32_t lmask) {
+                                            const StepCounter &sc, int tid, const PhiloxSweep &ps, Key2 key,
+                                            uint32_t nbh, uint32_t full, uint32_t lmask) {
     const int lane = tid & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), nw = NT / kWave;
     const RecView rv = rec_view(rec, orig, M);
-    if (kClust) return clause_phase_nb<kSample, kClust, 0>(L, rv, bnd, wave, nw, lane, ps, key, nbh, full, lmask);
-    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2>(L, rv, bnd, wave, nw, lane, ps, key, nbh, full, lmask)
-                   : clause_phase_nb<kSample, kClust, 1>(L, rv, bnd, wave, nw, lane, ps, key, nbh, full, lmask);
+    if (kClust) return clause_phase_nb<kSample, kClust, 0>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask);
+    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask)
+                   : clause_phase_nb<kSample, kClust, 1>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask);
 }
 
 // Range-relative length bounds of split member g of G: the member's run
@@ -839,6 +875,21 @@ __device__ __forceinline__ uint8_t visible_update(int64_t xi, double fx_scale, R
     return (Real(word >> 8) * Real(1.0 / 16777216.0)) < rho ? 1 : 0;
 }
 
+// The FP32 form: the logit from the two 32-bit halves of the fixed-point
+// sum (single-rate conversions; |x| error about 2^-24 |x|), the logistic
+// function from the hardware exp2 and reciprocal (about 2^-24 |x| + 2 ulp
+// relative in exp(-x), so |d rho| <= 0.25 of that: below 4e-7 for
+// |x| <= 20), the moving average and the draw in FP32.
+template <>
+__device__ __forceinline__ uint8_t visible_update<float>(int64_t xi, double fx_scale, float &nu, float alpha,
+                                                         uint32_t word) {
+    const float sc = (float)fx_scale;                          // 2^-S, exact
+    const float x = fmaf((float)(int32_t)(xi >> 32), sc * 4294967296.0f, (float)(uint32_t)xi * sc);
+    const float rho = __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+    nu = ema(nu, rho, alpha);
+    return ((float)(word >> 8) * (1.0f / 16777216.0f)) < rho ? 1 : 0;
+}
+
 // workgroup total of a per-thread count (uses L.cnt; ends with a barrier)
 __device__ __forceinline__ int block_total(const PushLds &L, int cnt, int tid, int NT) {
     cnt = wave_sum(cnt);
@@ -876,6 +927,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, W
     const int64_t t0 = *P.t_ptr;
 
     const int home = (int)(blockIdx.x % kXcds);
+    const int wave_id = __builtin_amdgcn_readfirstlane(tid / kWave);
     int qx = 0;                       // thread 0: ranges drained so far (own XCD first)
     for (int it = 0;; ++it) {
         int item;
@@ -945,6 +997,8 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, W
         const __amdgpu_buffer_rsrc_t neg_rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(negcnt), (short)0, N * 4, kRawBufferWord3);
         int smax = P.s_max[(int64_t)w.f * P.B + w.b];
+        const int steps = sweep_step_numbers(fd.lofs, NT);     // step numbers per sweep
+        if (tid == 0) L.cnt[62] = 0;
         __syncthreads();
 
         for (int64_t s = 0; s < S; ++s) {
@@ -958,8 +1012,11 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, W
                              : clause_phase_mfma<false>(L, rec, orig, C, tid, NT, tlo, thi, (uint32_t)w.b, key, nbh,
                                                         full, lmask, P.K, a1, a2, 1.0 / fx_scale);
             else
-                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, C, fd.lofs, tid, NT, ps, key, nbh, full, lmask)
-                             : clause_phase<false, kClust>(L, rec, orig, C, fd.lofs, tid, NT, ps, key, nbh, full, lmask);
+            {
+                const StepCounter sc{L.cnt + 62, (int)s * steps, P.dyn_steps, wave_id, NT / kWave};
+                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask)
+                             : clause_phase<false, kClust>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask);
+            }
             const int total = block_total(L, cnt, tid, NT);
             const bool improved = total > smax;
             if (improved) smax = total;
@@ -1073,6 +1130,7 @@ struct SplitCtx {
     int G, g, N, C, tid, NT, b, groups, q_lo, q_hi;
     int c_lo, c_hi;              // this member's run of records
     int32_t bnd[8];              // its records of length <= k, k = 0..7 (run-relative)
+    int steps;                   // clause-phase step numbers per sweep
     uint32_t nbh, full, lmask;
     bool sample;
 };
@@ -1144,10 +1202,12 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         // member g's records: every G-th of the length-sorted order (the same
         // mix of clause lengths for all members), stored as one contiguous run
         const PhiloxSweep ps = philox_sweep_consts(tlo, (uint32_t)c.b, thi, c.key);
+        const StepCounter sc{L.cnt + 62, (int)s * c.steps, 1, __builtin_amdgcn_readfirstlane(tid / kWave),
+                             NT / kWave};
         const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
-                                                              c.bnd, tid, NT, ps, c.key, c.nbh, c.full, c.lmask)
+                                                              c.bnd, sc, tid, ps, c.key, c.nbh, c.full, c.lmask)
                                  : clause_phase<false, kClust>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
-                                                               c.bnd, tid, NT, ps, c.key, c.nbh, c.full, c.lmask);
+                                                               c.bnd, sc, tid, ps, c.key, c.nbh, c.full, c.lmask);
         const int part = block_total(L, cnt, tid, NT);
         // publish the partial logits of the variables other members own
         if (c.sample) {
@@ -1291,6 +1351,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.c_lo = g * (fd.c / G) + min(g, fd.c % G);
     c.c_hi = c.c_lo + fd.c / G + (g < fd.c % G ? 1 : 0);
     member_bounds(fd.lofs, g, G, c.bnd);
+    c.steps = sweep_step_numbers(c.bnd, NT);
     c.tid = tid;
     c.NT = NT;
     c.b = w.b;
@@ -1335,6 +1396,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     }
     int smax = P.s_max[(int64_t)w.f * P.B + w.b];
     c.t0 = *P.t_ptr;
+    if (tid == 0) L.cnt[62] = 0;           // the clause-phase step counter
     __syncthreads();
 
     split_sweeps<Real, VPT, kClust>(P, Q, c, nu, ncr, smax);
@@ -1559,6 +1621,7 @@ SweepParams<Real> sweep_params(const Plan &p, const hp_state &st, int64_t n_swee
     P.L = p.L;
     P.B = p.B;
     P.lds_v_off = P.lds_x_off = P.lds_hm_off = 0;
+    P.dyn_steps = 1;
     return P;
 }
 
@@ -1629,6 +1692,7 @@ hipError_t launch_bucket_t(const Plan &p, const Bucket &b, const hp_state &st, i
     P.lds_v_off = b.v_off;
     P.lds_x_off = b.x_off;
     P.lds_hm_off = b.hm_off;
+    P.dyn_steps = b.dyn;
     if (b.kind == kBucketPull) {
         hipLaunchKernelGGL((void (*)(SweepParams<Real>))pull_kernel_ptr<Real>(b.vpt), dim3(b.count), dim3(b.threads),
                            b.lds, s, P);
