@@ -293,6 +293,12 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     std::vector<uint32_t> csr_ptr(NV + F);
     std::vector<uint32_t> occ((size_t)K * NC);
     std::vector<uint4> rec(NC);
+    // orig[]: the first Philox block of each record's hidden draw (the
+    // clause's input index times its blocks per clause, two in the
+    // size-clustered model), so the kernels add the unit's block offset only
+    const uint32_t blocks_per_clause = clust ? 2u : (uint32_t)(L + 3) / 4u;
+    if ((int64_t)max_c * blocks_per_clause > (int64_t(1) << 31))
+        return fail(HP_EUNSUPPORTED, "a formula's hidden draws would need more than 2^31 Philox blocks per sweep");
     std::vector<uint32_t> orig(NC);
     std::vector<uint32_t> push_slots(NV, 0);
     std::vector<int32_t> negcnt(NV, 0);
@@ -360,7 +366,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
             sl[7] = (uint16_t)(len | (negm << 3));
             rec[c0 + j] = make_uint4(sl[0] | ((uint32_t)sl[1] << 16), sl[2] | ((uint32_t)sl[3] << 16),
                                      sl[4] | ((uint32_t)sl[5] << 16), sl[6] | ((uint32_t)sl[7] << 16));
-            orig[c0 + j] = (uint32_t)(c - c0);
+            orig[c0 + j] = (uint32_t)(c - c0) * blocks_per_clause;
         }
         return std::string();
     };

@@ -95,7 +95,8 @@ struct ClustRbm {
 // 0..6 hold literal k as (0-based variable index) | (negated << 15); slot 7
 // holds len | (negation bits of slots 0..len-1) << 3, where len is the
 // clause length (positions >= len repeat literal 0).  Records of a formula
-// are sorted by len (stable); orig[] keeps the clause's index in the input,
+// are sorted by len (stable); orig[] keeps the first Philox block of the
+// clause's hidden draw, its index in the input times the blocks per clause,
 // which addresses its random numbers.
 //
 // thr[tau][m][l] holds 256 * ceil(2^24 p) - 1 (see the table kernel).
@@ -108,7 +109,7 @@ struct SweepParams {
     const uint32_t *csr_ptr;     // pull: per formula N_f+1 absolute offsets into occ
     const uint32_t *occ;         // pull: (c_local << 4) | (negated << 3) | k, (c, k) ascending
     const uint4 *rec;            // push: clause records [ctot]
-    const uint32_t *orig;        // push: input clause index [ctot]
+    const uint32_t *orig;        // push: first Philox block of the record's hidden draw [ctot]
     const int32_t *negcnt;       // push: negated slots per variable [sum N]
     const uint32_t *thr;         // [T][128][8]
     const Real *G;               // [T][256][8]

@@ -238,11 +238,19 @@ size_t lds_bytes_clust(int max_n, int32_t *v_off, int32_t *x_off) {
 // thresholds row[l] = 256 ceil(2^24 p_l) - 1 of its literal pattern, bit l
 // set iff word_l <= row[l] (i.e. U < p_l).  Units of the first Philox block
 // go to bits 0..3, of the second block (L > 4) to bits 4..7; bits >= L are
-// left to the caller to mask.
-template <int SH = 0>
-__device__ __forceinline__ uint32_t draw4(const uint4 &r, const uint4 &t) {
-    return (r.x <= t.x ? 1u << SH : 0u) | (r.y <= t.y ? 2u << SH : 0u) | (r.z <= t.z ? 4u << SH : 0u) |
-           (r.w <= t.w ? 8u << SH : 0u);
+// left to the caller to mask.  The bits are shifted in one unit at a time,
+// from the highest unit down so that unit l lands on bit l: the compare's
+// lane mask is the carry-in of an add that doubles the mask, two VALU
+// instructions per unit (a compare, a select and part of an OR in the plain
+// C form).
+__device__ __forceinline__ uint32_t draw_first(uint32_t w, uint32_t t) {
+    uint32_t m;
+    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_e64 %0, 0, 1, vcc" : "=v"(m) : "v"(w), "v"(t) : "vcc");
+    return m;
+}
+__device__ __forceinline__ uint32_t draw_next(uint32_t m, uint32_t w, uint32_t t) {
+    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc" : "+v"(m) : "v"(w), "v"(t) : "vcc");
+    return m;
 }
 
 // NB: Philox blocks per clause, 1 (L <= 4) or 2 (L <= 8); 0 = read nbh at run time
@@ -256,9 +264,20 @@ __device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t bl
         uint4 r[2];
         const uint32_t w[2] = {kPhaseHidden | blk, kPhaseHidden | (blk + 1u)};
         philox_sweep_multi<2>(r, w, u, key);
-        return draw4<0>(r[0], ta) | draw4<4>(r[1], tb);
+        uint32_t m = draw_first(r[1].w, tb.w);
+        m = draw_next(m, r[1].z, tb.z);
+        m = draw_next(m, r[1].y, tb.y);
+        m = draw_next(m, r[1].x, tb.x);
+        m = draw_next(m, r[0].w, ta.w);
+        m = draw_next(m, r[0].z, ta.z);
+        m = draw_next(m, r[0].y, ta.y);
+        return draw_next(m, r[0].x, ta.x);
     }
-    return draw4(philox_sweep(kPhaseHidden | blk, u, key), ta);
+    const uint4 r = philox_sweep(kPhaseHidden | blk, u, key);
+    uint32_t m = draw_first(r.w, ta.w);
+    m = draw_next(m, r.z, ta.z);
+    m = draw_next(m, r.y, ta.y);
+    return draw_next(m, r.x, ta.x);
 }
 
 // VPT > 0: each thread owns VPT groups of 4 consecutive variables and keeps
@@ -564,12 +583,13 @@ __device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint
         if (kClust) {
             constexpr uint32_t Kc = LEN < 3 ? 3u : (uint32_t)LEN;
             constexpr bool big = Kc > 3u;                            // L = K + 1 > 4: two blocks
-            n = hidden_mask<big ? 2 : 1>(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc * 2u, ps, key, 0u) &
+            n = hidden_mask<big ? 2 : 1>(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc, ps, key, 0u) &
                 (big ? (2u << Kc) - 1u : 7u);
             g0 = L.gpad[(LEN <= 3 ? 8u * (LEN - 1u) : (2u << LEN) - 8u) + n];
             gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
         } else {
-            n = hidden_mask<NB>(L.thr + m * kMaxL, oc << (NB > 1 ? 1 : 0), ps, key, 0u) & lmask;
+            n = hidden_mask<NB>(L.thr + m * kMaxL, oc, ps, key, 0u);
+            if (lmask != (NB > 1 ? 0xFFu : 0xFu)) n &= lmask;        // uniform: L < 4 NB only
             g0 = L.gpad[LEN * kHidMasks + n];
             gr = L.gfx + n * kMaxL;
         }
@@ -579,8 +599,8 @@ __device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint
 }
 
 // A wave's view of a range of clause records: raw buffer descriptors over
-// the records and their input indices (loads past the range return zeros),
-// so a load of 64 consecutive records takes a wave-uniform byte offset in a
+// the records and their first hidden-draw blocks (loads past the range
+// return zeros), so a load of 64 consecutive records takes a wave-uniform byte offset in a
 // scalar register and the lane's fixed offset in a vector register.
 struct RecView {
     __amdgpu_buffer_rsrc_t rec, orig;
@@ -621,10 +641,22 @@ struct StepCounter {
     int wave, nw;
 };
 
+// One LDS add-and-return of 1 by the calling lane.  The compiler's atomic
+// form wraps an add at a uniform address in a whole-wave reduction (lane
+// counts, prefix, two broadcasts: 8 VALU instructions per step, i.e. per
+// clause); here only the add and the wait for its result, which sits in the
+// same asm block so the returned register is never read early.
+__device__ __forceinline__ int lds_fetch_add1(int *p) {
+    const uint32_t a = (uint32_t)(size_t)(__attribute__((address_space(3))) int *)p;
+    int k;
+    asm volatile("ds_add_rtn_u32 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=v"(k) : "v"(a), "v"(1) : "memory");
+    return k;
+}
+
 __device__ __forceinline__ int take_step(const StepCounter &sc, int lane, int prev) {
     if (!sc.dyn) return prev < 0 ? sc.wave : prev + sc.nw;
     int k = 0;
-    if (lane == 0) k = atomicAdd(sc.ctr, 1);
+    if (lane == 0) k = lds_fetch_add1(sc.ctr);
     return __builtin_amdgcn_readfirstlane(k) - sc.base;
 }
 
@@ -798,7 +830,7 @@ __device__ __forceinline__ int clause_phase_mfma(const PushLds &L, const uint4 *
         // ---- hidden logits z = b + W^T lit, limb pairs summed in FP32 ----
         const f32x16_t d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bits_bf16x8(act ? (m | 0x80u) : 0u),
                                                                     f32x16_t{}, 0, 0, 0);
-        const uint4 rw = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | (oc * nbh + (uint32_t)half), thi), key);
+        const uint4 rw = philox4x32_10(make_uint4(tlo, chain, kPhaseHidden | (oc + (uint32_t)half), thi), key);
         const uint32_t w4[4] = {rw.x, rw.y, rw.z, rw.w};
         uint32_t nh = 0, amb = 0;
 #pragma unroll
