@@ -168,7 +168,7 @@ typedef struct hp_plan_s *hp_plan_t;
  * temperature index outside [0, n_temps).  HP_EUNSUPPORTED: N_f > 32768, or
  * a formula whose working set exceeds the workgroup's LDS (160 KB on gfx950:
  * the push kernels take 9 bytes per variable plus their tables, which covers
- * N_f up to about 17 700; beyond that the pull kernel needs about
+ * N_f up to about 17 200; beyond that the pull kernel needs about
  * 20 KB + N_f + C_f bytes). */
 hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm,
                   const hp_opts *opts, void *stream);

@@ -687,8 +687,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         HP_TRY(hipMalloc((void **)&p->tab.thr, (size_t)T * kPatterns * kMaxL * sizeof(uint32_t)), "alloc thr");
         HP_TRY(hipMalloc((void **)&p->tab.g64, (size_t)T * kHidMasks * kMaxL * sizeof(double)), "alloc g64");
         HP_TRY(hipMalloc((void **)&p->tab.g32, (size_t)T * kHidMasks * kMaxL * sizeof(float)), "alloc g32");
-        HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kMaxL * sizeof(int64_t)), "alloc gfx");
-        HP_TRY(hipMalloc((void **)&p->tab.gpad, (size_t)T * kMaxL * kHidMasks * sizeof(int64_t)), "alloc gpad");
+        HP_TRY(hipMalloc((void **)&p->tab.gfx, (size_t)T * kHidMasks * kRowWords * sizeof(int64_t)), "alloc gfx");
     }
     if (mixed) {
         std::vector<uint4> ops;

@@ -13,6 +13,8 @@ namespace hp {
 constexpr int kMaxK = 7;          // clause width limit (Sec. 3.1 assumes K <= 7)
 constexpr int kMaxL = 8;          // hidden units per clause: K+1 <= 8
 constexpr int kPatterns = 128;    // literal-truth patterns over K <= 7 inputs
+constexpr int kThrRows = 2 * kPatterns;   // push kernels: rows 2^len - 2 + (pattern of the len literals)
+constexpr int kRowWords = 16;     // contribution table row: 8 slot words, 8 merged-padding words
 constexpr int kHidMasks = 256;    // hidden-state masks over L <= 8 units
 constexpr int kMaxVars = 32768;   // variable index packed in 15 bits
 constexpr int kWave = 64;
@@ -40,16 +42,17 @@ struct WorkItem {
 //   G[tau][n][k]  = sum_{l ascending, bit_l(n)} W_c[k,l]
 //       so that the contribution of clause c to its k-th input is
 //       pol_kc * G[tau][h-mask][k]  (the vector l^(c) = W_f^(c) h^(c));
-//   gfx[tau][n][k] = round(G * 2^S) as int64 (fixed point, scale 2^S);
-//   gpad[tau][len][n] = gfx[n][0] + sum_{k = len}^{K-1} gfx[n][k]: the
-//       merged contribution of a clause's first literal and its padding
-//       copies (Sec. 3.3 pads by repeating a literal).
+//   gfx[tau][n][k] = round(G * 2^S) as int64 (fixed point, scale 2^S) for
+//       k < 8, and gfx[tau][n][8 + len] = gfx[n][0] + sum_{k = len}^{K-1}
+//       gfx[n][k] for len = 1..K: the merged contribution of a clause's
+//       first literal and its padding copies (Sec. 3.3 pads by repeating a
+//       literal); rows n >= 2^L repeat row n mod 2^L.
 struct DeviceTables {
     uint32_t *thr = nullptr;   // [T][128][8]
     double *g64 = nullptr;     // [T][256][8]
     float *g32 = nullptr;      // [T][256][8]
-    int64_t *gfx = nullptr;    // [T][256][8]
-    int64_t *gpad = nullptr;   // [T][8][256]
+    int64_t *gfx = nullptr;    // [T][256][16] (size-clustered model: its own layout)
+    int64_t *gpad = nullptr;   // size-clustered model only
     uint4 *mfma = nullptr;     // [T][2][64] per-lane BF16 limb operands (mixed precision)
 };
 
@@ -113,8 +116,8 @@ struct SweepParams {
     const int32_t *negcnt;       // push: negated slots per variable [sum N]
     const uint32_t *thr;         // [T][128][8]
     const Real *G;               // [T][256][8]
-    const int64_t *gfx;          // [T][256][8]
-    const int64_t *gpad;         // [T][8][256]
+    const int64_t *gfx;          // [T][256][16] contribution rows (size-clustered: its layout)
+    const int64_t *gpad;         // size-clustered model's merged paddings
     const uint4 *mfma;           // [T][2][64] mixed-precision A operands
     const int32_t *temp_of_chain;  // [F][B] temperature index per (formula, chain)
     uint8_t *v;
@@ -155,9 +158,9 @@ enum class Variant { kPull = 0, kPush = 1 };
 
 // A launch over a contiguous range of work items: formulas of one size class
 // and one kernel variant, with its own workgroup size and LDS footprint.
-// push: every table in LDS; mid: the merged padding table gpad read from
-// global memory (one read per clause), the rest in LDS; wide: both
-// contribution tables in global memory (the largest formulas)
+// push: every table in LDS; mid: the merged padding words read from global
+// memory (one read per clause), the rest in LDS; wide: the contribution
+// rows in global memory (the largest formulas)
 // XCDs of the GPU (MI355X: 8 compute dies, each with its own L2); workgroup
 // w of a launch is dispatched to XCD w mod 8
 constexpr int kXcds = 8;

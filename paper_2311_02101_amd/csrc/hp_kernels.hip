@@ -47,9 +47,11 @@ namespace hp {
 // Plan tables (once per plan)
 // --------------------------------------------------------------------------
 __device__ double g_entry(const double *__restrict__ Wt, int K, int L, int n, int k) {
-    // G[n][k] = sum over the set bits l of n, ascending, of W_c[k,l]
+    // G[n][k] = sum over the set bits l < L of n, ascending, of W_c[k,l]; the
+    // bits of n at and above L are ignored, so rows n >= 2^L repeat row
+    // n mod 2^L (the push kernels index them with undrawn high units)
     double acc = 0.0;
-    if (k < K && n < (1 << L))
+    if (k < K)
         for (int l = 0; l < L; ++l)
             if ((n >> l) & 1) acc += Wt[k * L + l];
     return acc;
@@ -61,11 +63,11 @@ __device__ int64_t g_fixed(const double *__restrict__ Wt, int K, int L, int n, i
 
 __global__ void tables_kernel(const double *__restrict__ W, const double *__restrict__ b, int K, int L,
                               int T, int S, uint32_t *__restrict__ thr, double *__restrict__ g64,
-                              float *__restrict__ g32, int64_t *__restrict__ gfx,
-                              int64_t *__restrict__ gpad, int32_t *__restrict__ flag) {
+                              float *__restrict__ g32, int64_t *__restrict__ gtab, int32_t *__restrict__ flag) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int n_thr = T * kPatterns * kMaxL;
     const int n_g = T * kHidMasks * kMaxL;
+    const int n_tab = T * kHidMasks * kRowWords;
     if (tid < n_thr) {
         const int tau = tid / (kPatterns * kMaxL);
         const int m = (tid / kMaxL) % kPatterns;
@@ -93,16 +95,22 @@ __global__ void tables_kernel(const double *__restrict__ W, const double *__rest
         const double acc = g_entry(Wt, K, L, n, k);
         g64[tid] = acc;
         g32[tid] = (float)acc;
-        gfx[tid] = g_fixed(Wt, K, L, n, k, S);
-        // gpad[tau][len][n], same flat range: len = tid / 256 % 8, n = tid % 256
-        const int len = (tid / kHidMasks) % kMaxL;
-        const int n2 = tid % kHidMasks;
-        int64_t acc2 = 0;
-        if (len >= 1 && len <= K) {
-            acc2 = g_fixed(Wt, K, L, n2, 0, S);
-            for (int kk = len; kk < K; ++kk) acc2 += g_fixed(Wt, K, L, n2, kk, S);
+    }
+    if (tid < n_tab) {
+        // gtab[tau][n][j]: j < 8 the fixed-point G[n][j]; j = 8 + len the
+        // merged contribution of a clause of len literals to its first one
+        const int tau = tid / (kHidMasks * kRowWords);
+        const int n = (tid / kRowWords) % kHidMasks;
+        const int j = tid % kRowWords;
+        const double *Wt = W + (size_t)tau * K * L;
+        int64_t out = 0;
+        if (j < kMaxL) {
+            out = g_fixed(Wt, K, L, n, j, S);
+        } else if (j - kMaxL >= 1 && j - kMaxL <= K) {
+            out = g_fixed(Wt, K, L, n, 0, S);
+            for (int kk = j - kMaxL; kk < K; ++kk) out += g_fixed(Wt, K, L, n, kk, S);
         }
-        gpad[tid] = acc2;
+        gtab[tid] = out;
     }
 }
 
@@ -159,9 +167,9 @@ hipError_t launch_tables(const Plan &p, hipStream_t s) {
                                                             p.tab.gpad, p.d_tabflag);
         return hipGetLastError();
     }
-    const int n = p.T * kHidMasks * kMaxL;   // >= the threshold table size
+    const int n = p.T * kHidMasks * kRowWords;   // the largest of the three tables
     tables_kernel<<<(n + 255) / 256, 256, 0, s>>>(p.d_W, p.d_b, p.K, p.L, p.T, p.fx_shift, p.tab.thr,
-                                                  p.tab.g64, p.tab.g32, p.tab.gfx, p.tab.gpad, p.d_tabflag);
+                                                  p.tab.g64, p.tab.g32, p.tab.gfx, p.d_tabflag);
     return hipGetLastError();
 }
 
@@ -194,19 +202,26 @@ size_t lds_bytes_pull(int max_n, int max_c, size_t real_bytes, int32_t *v_off, i
     return off;
 }
 
-// push LDS layout: thr (4 KB) | gfx (16 KB) | gpad (16 KB) | counts | v (1 B/var) | x (8 B/var)
-constexpr int kPushGfxOff = kPatterns * kMaxL * 4;
-constexpr int kPushGpadOff = kPushGfxOff + kHidMasks * kMaxL * 8;
-constexpr int kPushCntOff = kPushGpadOff + kMaxL * kHidMasks * 8;
+// push LDS layout: thr (8 KB) | table rows (32 KB) | counts | v (1 B/var) | x (8 B/var)
+// The push kernels' threshold rows are indexed by clause length and the
+// pattern of the clause's own literals: row 2^len - 2 + m for len = 1..7
+// holds the row of the padded pattern (m with positions >= len copying bit
+// 0), so the clause loop never builds the padding bits.
+// The contribution table of the padded model has one 128-byte row per
+// hidden mask n: words 0..7 the slot contributions, word 8 + len the merged
+// contribution of a clause of len literals to its first one, so one offset
+// n * 128 addresses both of a clause's reads.
+constexpr int kPushTabOff = kThrRows * kMaxL * 4;
+constexpr int kPushCntOff = kPushTabOff + kHidMasks * kRowWords * 8;
 constexpr int kPushVOff = kPushCntOff + 64 * 4;
 
-// wide layout (G tables read from global memory): thr | counts | v | x
-constexpr int kWideCntOff = kPatterns * kMaxL * 4;
+// wide layout (table rows read from global memory): thr | counts | v | x
+constexpr int kWideCntOff = kThrRows * kMaxL * 4;
 constexpr int kWideVOff = kWideCntOff + 64 * 4;
 
-// middle layout (only the merged padding table gpad, one read per clause,
-// from global memory): thr | gfx | counts | v | x
-constexpr int kMidGfxOff = kPatterns * kMaxL * 4;
+// middle layout (only the merged padding words, one read per clause, from
+// global memory): thr | slot contributions (rows of 8) | counts | v | x
+constexpr int kMidGfxOff = kThrRows * kMaxL * 4;
 constexpr int kMidCntOff = kMidGfxOff + kHidMasks * kMaxL * 8;
 constexpr int kMidVOff = kMidCntOff + 64 * 4;
 
@@ -450,7 +465,14 @@ __device__ __forceinline__ unsigned char *lds_at(int off) {
     return (unsigned char *)(__attribute__((address_space(3))) unsigned char *)(size_t)off;
 }
 
-// LDS views of the push layout
+// the third descriptor word of a raw (untyped) buffer on gfx9-family GPUs
+constexpr int kRawBufferWord3 = 0x00020000;
+
+// Views of a push layout: LDS regions, plus a buffer descriptor over the
+// global table rows of the chain's temperature (mid and wide layouts).
+// gfx: the table rows (push layout, rows of 16 words), the slot
+// contributions (mid layout, rows of 8) or the size-clustered model's
+// contribution rows; gpad: the size-clustered model's merged paddings.
 struct PushLds {
     uint32_t *thr;
     int64_t *gfx;
@@ -458,61 +480,76 @@ struct PushLds {
     int *cnt;
     int64_t *x;
     uint8_t *v;
+    __amdgpu_buffer_rsrc_t grs;
 };
 
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rows(const int64_t *gtab, int tau) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<int64_t *>(gtab + (size_t)tau * kHidMasks * kRowWords),
+                                             (short)0, kHidMasks * kRowWords * 8, kRawBufferWord3);
+}
+
+// an empty descriptor (every load through it returns zeros) for the layouts
+// that read no table from global memory
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t no_rows() {
+    return __builtin_amdgcn_make_buffer_rsrc(nullptr, (short)0, 0, kRawBufferWord3);
+}
+
 __device__ __forceinline__ PushLds push_lds(unsigned char *lds, int x_off) {
-    return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kPushGfxOff)),
-                   reinterpret_cast<int64_t *>(lds_at(kPushGpadOff)), reinterpret_cast<int *>(lds + kPushCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kPushVOff)};
+    return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kPushTabOff)),
+                   nullptr, reinterpret_cast<int *>(lds + kPushCntOff), reinterpret_cast<int64_t *>(lds + x_off),
+                   lds_at(kPushVOff), no_rows()};
 }
 
-// wide variant: the G tables of temperature tau stay in global memory
-__device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, const int64_t *gfx,
-                                                 const int64_t *gpad, int tau) {
-    return PushLds{reinterpret_cast<uint32_t *>(lds), const_cast<int64_t *>(gfx + tau * kHidMasks * kMaxL),
-                   const_cast<int64_t *>(gpad + tau * kHidMasks * kMaxL),
-                   reinterpret_cast<int *>(lds + kWideCntOff), reinterpret_cast<int64_t *>(lds + x_off),
-                   lds_at(kWideVOff)};
+// wide variant: the table rows of temperature tau stay in global memory
+__device__ __forceinline__ PushLds push_lds_wide(unsigned char *lds, int x_off, const int64_t *gtab, int tau) {
+    return PushLds{reinterpret_cast<uint32_t *>(lds), nullptr, nullptr, reinterpret_cast<int *>(lds + kWideCntOff),
+                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kWideVOff), table_rows(gtab, tau)};
 }
 
-// middle variant: gpad of temperature tau stays in global memory
-__device__ __forceinline__ PushLds push_lds_mid(unsigned char *lds, int x_off, const int64_t *gpad, int tau) {
+// middle variant: the merged paddings of temperature tau stay in global memory
+__device__ __forceinline__ PushLds push_lds_mid(unsigned char *lds, int x_off, const int64_t *gtab, int tau) {
     return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kMidGfxOff)),
-                   const_cast<int64_t *>(gpad + tau * kHidMasks * kMaxL), reinterpret_cast<int *>(lds + kMidCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kMidVOff)};
+                   nullptr, reinterpret_cast<int *>(lds + kMidCntOff), reinterpret_cast<int64_t *>(lds + x_off),
+                   lds_at(kMidVOff), table_rows(gtab, tau)};
 }
 
 template <int kTab>
-__device__ __forceinline__ PushLds push_lds_for(unsigned char *lds, int x_off, const int64_t *gfx, const int64_t *gpad,
-                                                int tau) {
-    if (kTab == kBucketWide) return push_lds_wide(lds, x_off, gfx, gpad, tau);
-    if (kTab == kBucketMid) return push_lds_mid(lds, x_off, gpad, tau);
+__device__ __forceinline__ PushLds push_lds_for(unsigned char *lds, int x_off, const int64_t *gtab, int tau) {
+    if (kTab == kBucketWide) return push_lds_wide(lds, x_off, gtab, tau);
+    if (kTab == kBucketMid) return push_lds_mid(lds, x_off, gtab, tau);
     return push_lds(lds, x_off);
 }
 
 __device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off) {
     return PushLds{reinterpret_cast<uint32_t *>(lds_at(0)), reinterpret_cast<int64_t *>(lds_at(kClustGfxOff)),
                    reinterpret_cast<int64_t *>(lds_at(kClustGpadOff)), reinterpret_cast<int *>(lds + kClustCntOff),
-                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kClustVOff)};
+                   reinterpret_cast<int64_t *>(lds + x_off), lds_at(kClustVOff), no_rows()};
+}
+
+// row of the padded pattern for row r = 2^len - 2 + m of the push kernels'
+// per-length threshold table (full = 2^K - 1; rows with len > K are unused)
+__device__ __forceinline__ uint32_t padded_row(uint32_t r, uint32_t full) {
+    const uint32_t len = 31u - (uint32_t)__clz((int)(r + 2u));
+    const uint32_t m = r + 2u - (1u << len);
+    return (m | ((m & 1u) ? ~((1u << len) - 1u) : 0u)) & full;
 }
 
 template <int kTab, bool kClust = false>
 __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_t *thr, const int64_t *gfx,
-                                                 const int64_t *gpad, int tau, int tid, int NT) {
+                                                 const int64_t *gpad, int tau, int tid, int NT, uint32_t full) {
     if (kClust) {
         for (int i = tid; i < kClustThrRows * kMaxL; i += NT) L.thr[i] = thr[tau * kClustThrRows * kMaxL + i];
         for (int i = tid; i < kClustGfxRows * kMaxL; i += NT) L.gfx[i] = gfx[tau * kClustGfxRows * kMaxL + i];
         for (int i = tid; i < kClustGpad; i += NT) L.gpad[i] = gpad[tau * kClustGpad + i];
         return;
     }
-    for (int i = tid; i < kPatterns * kMaxL; i += NT) L.thr[i] = thr[tau * kPatterns * kMaxL + i];
+    for (int i = tid; i < (kThrRows - 2) * kMaxL; i += NT)
+        L.thr[i] = thr[(tau * kPatterns + (int)padded_row((uint32_t)(i / kMaxL), full)) * kMaxL + i % kMaxL];
+    const int64_t *rows = gfx + (size_t)tau * kHidMasks * kRowWords;
     if (kTab == kBucketPush) {
-        for (int i = tid; i < kHidMasks * kMaxL; i += NT) {
-            L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
-            L.gpad[i] = gpad[tau * kHidMasks * kMaxL + i];
-        }
+        for (int i = tid; i < kHidMasks * kRowWords; i += NT) L.gfx[i] = rows[i];
     } else if (kTab == kBucketMid) {
-        for (int i = tid; i < kHidMasks * kMaxL; i += NT) L.gfx[i] = gfx[tau * kHidMasks * kMaxL + i];
+        for (int i = tid; i < kHidMasks * kMaxL; i += NT) L.gfx[i] = rows[(i / kMaxL) * kRowWords + i % kMaxL];
     }
 }
 
@@ -554,16 +591,33 @@ __device__ __forceinline__ void scatter_slots(int64_t *x, const uint4 &r, const 
     }
 }
 
-// All of the clause's table entries are read before the first accumulator
-// update: the compiler cannot tell that the atomics never touch the tables,
-// so reads placed after an atomic would each wait for it.
-template <int LEN>
-__device__ __forceinline__ void scatter_fixed(int64_t *x, const uint4 &r, int64_t g0, const int64_t *gr) {
-    int64_t g[8];
-    g[0] = g0;
+__device__ __forceinline__ int64_t buffer_load_i64(__amdgpu_buffer_rsrc_t rs, int off) {
+    return __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+
+// The contributions of hidden mask n to a clause of LEN literals: g[0] the
+// merged one of slot 0 (with its padding copies), g[k] slot k's.  All of them
+// are read before the first accumulator update: the compiler cannot tell
+// that the atomics never touch the tables, so reads placed after an atomic
+// would each wait for it.
+template <int LEN, int kTab>
+__device__ __forceinline__ void table_reads(const PushLds &L, uint32_t n, int64_t (&g)[8]) {
+    const int off = (int)n * (kRowWords * 8);
+    if (kTab == kBucketPush) {
+        const int64_t *row = L.gfx + n * kRowWords;
+        g[0] = row[kMaxL + LEN];
 #pragma unroll
-    for (int k = 1; k < LEN; ++k) g[k] = gr[k];
-    scatter_slots<0, LEN>(x, r, g);
+        for (int k = 1; k < LEN; ++k) g[k] = row[k];
+    } else if (kTab == kBucketMid) {
+        const int64_t *row = L.gfx + n * kMaxL;
+        g[0] = buffer_load_i64(L.grs, off + (kMaxL + LEN) * 8);
+#pragma unroll
+        for (int k = 1; k < LEN; ++k) g[k] = row[k];
+    } else {
+        g[0] = buffer_load_i64(L.grs, off + (kMaxL + LEN) * 8);
+#pragma unroll
+        for (int k = 1; k < LEN; ++k) g[k] = buffer_load_i64(L.grs, off + k * 8);
+    }
 }
 
 // One clause of compile-time length LEN: gather, literal-truth pattern,
@@ -572,28 +626,30 @@ __device__ __forceinline__ void scatter_fixed(int64_t *x, const uint4 &r, int64_
 // kClust: the size-clustered model; a clause of length len takes the tables
 // of group K = max(len, 3) (L = 3 or K + 1 hidden units, drawn from blocks
 // 2c and, for L > 4, 2c + 1), and nbh, full and lmask are unused.
-template <int LEN, bool kSample, bool kClust, int NB>
+template <int LEN, bool kSample, bool kClust, int NB, int kTab>
 __device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint32_t oc, const PhiloxSweep &ps,
                                           Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
-    const uint32_t m = pattern_fixed<LEN, kClust>(L.v, r, full);
+    // size-clustered model: the padded pattern; padded model: the pattern of
+    // the LEN literals alone (its threshold row holds the padded one's)
+    const uint32_t m = kClust ? pattern_fixed<LEN, kClust>(L.v, r, full) : gather_fixed<LEN>(L.v, r) ^ (r.w >> 19);
     if (kSample) {
-        uint32_t n;
-        int64_t g0;
-        const int64_t *gr;
+        int64_t g[8];
         if (kClust) {
             constexpr uint32_t Kc = LEN < 3 ? 3u : (uint32_t)LEN;
             constexpr bool big = Kc > 3u;                            // L = K + 1 > 4: two blocks
-            n = hidden_mask<big ? 2 : 1>(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc, ps, key, 0u) &
-                (big ? (2u << Kc) - 1u : 7u);
-            g0 = L.gpad[(LEN <= 3 ? 8u * (LEN - 1u) : (2u << LEN) - 8u) + n];
-            gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
+            const uint32_t n = hidden_mask<big ? 2 : 1>(L.thr + ((1u << Kc) - 8u + m) * kMaxL, oc, ps, key, 0u) &
+                               (big ? (2u << Kc) - 1u : 7u);
+            const int64_t *gr = L.gfx + ((big ? (2u << Kc) - 24u : 0u) + n) * kMaxL;
+            g[0] = L.gpad[(LEN <= 3 ? 8u * (LEN - 1u) : (2u << LEN) - 8u) + n];
+#pragma unroll
+            for (int k = 1; k < LEN; ++k) g[k] = gr[k];
         } else {
-            n = hidden_mask<NB>(L.thr + m * kMaxL, oc, ps, key, 0u);
-            if (lmask != (NB > 1 ? 0xFFu : 0xFu)) n &= lmask;        // uniform: L < 4 NB only
-            g0 = L.gpad[LEN * kHidMasks + n];
-            gr = L.gfx + n * kMaxL;
+            // units at and above L (drawn, not masked) index rows that
+            // repeat row n mod 2^L
+            const uint32_t n = hidden_mask<NB>(L.thr + ((1u << LEN) - 2u + m) * kMaxL, oc, ps, key, 0u);
+            table_reads<LEN, kTab>(L, n, g);
         }
-        scatter_fixed<LEN>(L.x, r, g0, gr);
+        scatter_slots<0, LEN>(L.x, r, g);
     }
     return m != 0u ? 1 : 0;
 }
@@ -605,9 +661,6 @@ __device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint
 struct RecView {
     __amdgpu_buffer_rsrc_t rec, orig;
 };
-
-// the third descriptor word of a raw (untyped) buffer on gfx9-family GPUs
-constexpr int kRawBufferWord3 = 0x00020000;
 
 __device__ __forceinline__ RecView rec_view(const uint4 *rec, const uint32_t *orig, int M) {
     return RecView{__builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(rec), (short)0, M * 16, kRawBufferWord3),
@@ -665,7 +718,7 @@ __device__ __forceinline__ int take_step(const StepCounter &sc, int lane, int pr
 // processes it and keeps taking steps until it gets one past the run, which
 // it leaves in `k` for the next run.  The next step's records are loaded
 // while the current ones are processed (two register sets, no copies).
-template <int LEN, bool kSample, bool kClust, int NB>
+template <int LEN, bool kSample, bool kClust, int NB, int kTab>
 __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int olo, int ohi,
                                               int &k, const StepCounter &sc, int lane, const PhiloxSweep &ps,
                                               Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
@@ -679,14 +732,14 @@ __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &r
         int kn = take_step(sc, lane, k);
         int next = lo + (kn - olo) * kWave;
         if (kn < ohi) rec_load(rv, next, lane, rb, ob);
-        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB>(L, ra, oa, ps, key, nbh, full, lmask);
+        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB, kTab>(L, ra, oa, ps, key, nbh, full, lmask);
         k = kn;
         if (kn >= ohi) break;
         base = next;
         kn = take_step(sc, lane, k);
         next = lo + (kn - olo) * kWave;
         if (kn < ohi) rec_load(rv, next, lane, ra, oa);
-        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB>(L, rb, ob, ps, key, nbh, full, lmask);
+        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB, kTab>(L, rb, ob, ps, key, nbh, full, lmask);
         k = kn;
         if (kn >= ohi) break;
         base = next;
@@ -707,7 +760,7 @@ __device__ __forceinline__ void run_steps(const int32_t (&bnd)[8], int32_t (&o)[
 // length by length in steps of 64 (above), so every step is one clause
 // length (the gather and scatter unrolled for it) with no per-record length
 // test.  Returns this thread's number of satisfied clauses.
-template <bool kSample, bool kClust, int NB>
+template <bool kSample, bool kClust, int NB, int kTab>
 __device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &rv, const int32_t (&bnd)[8],
                                                const StepCounter &sc, int lane, const PhiloxSweep &ps, Key2 key,
                                                uint32_t nbh, uint32_t full, uint32_t lmask) {
@@ -716,8 +769,8 @@ __device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &
     int cnt = 0;
     int k = take_step(sc, lane, -1);
 #define HP_SEG(LEN)                                                                                              \
-    cnt += clause_segment<LEN, kSample, kClust, NB>(L, rv, bnd[LEN - 1], bnd[LEN], o[LEN - 1], o[LEN], k, sc,    \
-                                                    lane, ps, key, nbh, full, lmask)
+    cnt += clause_segment<LEN, kSample, kClust, NB, kTab>(L, rv, bnd[LEN - 1], bnd[LEN], o[LEN - 1], o[LEN], k,  \
+                                                          sc, lane, ps, key, nbh, full, lmask)
     HP_SEG(1);
     HP_SEG(2);
     HP_SEG(3);
@@ -736,16 +789,16 @@ __device__ __forceinline__ int sweep_step_numbers(const int32_t (&bnd)[8], int N
     return o[7] + NT / kWave;
 }
 
-template <bool kSample, bool kClust>
+template <bool kSample, bool kClust, int kTab>
 __device__ __forceinline__ int clause_phase(const PushLds &L, const uint4 *__restrict__ rec,
                                             const uint32_t *__restrict__ orig, int M, const int32_t (&bnd)[8],
                                             const StepCounter &sc, int tid, const PhiloxSweep &ps, Key2 key,
                                             uint32_t nbh, uint32_t full, uint32_t lmask) {
     const int lane = tid & (kWave - 1);
     const RecView rv = rec_view(rec, orig, M);
-    if (kClust) return clause_phase_nb<kSample, kClust, 0>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask);
-    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask)
-                   : clause_phase_nb<kSample, kClust, 1>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask);
+    if (kClust) return clause_phase_nb<kSample, kClust, 0, kTab>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask);
+    return nbh > 1 ? clause_phase_nb<kSample, kClust, 2, kTab>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask)
+                   : clause_phase_nb<kSample, kClust, 1, kTab>(L, rv, bnd, sc, lane, ps, key, nbh, full, lmask);
 }
 
 // Range-relative length bounds of split member g of G: the member's run
@@ -845,7 +898,8 @@ __device__ __forceinline__ int clause_phase_mfma(const PushLds &L, const uint4 *
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if ((amb >> q) & 1u) {
-                    const uint32_t bit = w4[q] <= L.thr[m * kMaxL + 4 * half + q] ? 1u : 0u;
+                    const uint32_t row = (1u << len) - 2u + (m & ((1u << len) - 1u));
+                    const uint32_t bit = w4[q] <= L.thr[row * kMaxL + 4 * half + q] ? 1u : 0u;
                     nh = (nh & ~(1u << q)) | (bit << q);
                 }
         }
@@ -991,14 +1045,14 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, W
         const int N = fd.n, C = fd.c;
         const int tau = P.temp_of_chain[(int64_t)w.f * P.B + w.b];
         const PushLds L = kClust ? push_lds_clust(lds, P.lds_x_off)
-                                 : push_lds_for<kTab>(lds, P.lds_x_off, P.gfx, P.gpad, tau);
+                                 : push_lds_for<kTab>(lds, P.lds_x_off, P.gfx, tau);
         const int64_t sbase = fd.var_off * P.B + (int64_t)w.b * N;
         const uint4 *__restrict__ rec = P.rec + fd.clause_off;
         const uint32_t *__restrict__ orig = P.orig + fd.clause_off;
         const Key2 key{P.key0, P.key1 ^ (uint32_t)w.f};
         const int32_t *__restrict__ negcnt = P.negcnt + fd.var_off;
 
-        load_push_tables<kTab, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+        load_push_tables<kTab, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT, full);
         for (int i = tid; i < N; i += NT) {
             L.v[i] = P.v[sbase + i];
             L.x[i] = negcnt[i];
@@ -1046,8 +1100,8 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, W
             else
             {
                 const StepCounter sc{L.cnt + 62, (int)s * steps, P.dyn_steps, wave_id, NT / kWave};
-                cnt = sample ? clause_phase<true, kClust>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask)
-                             : clause_phase<false, kClust>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask);
+                cnt = sample ? clause_phase<true, kClust, kTab>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask)
+                             : clause_phase<false, kClust, kTab>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask);
             }
             const int total = block_total(L, cnt, tid, NT);
             const bool improved = total > smax;
@@ -1236,9 +1290,9 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         const PhiloxSweep ps = philox_sweep_consts(tlo, (uint32_t)c.b, thi, c.key);
         const StepCounter sc{L.cnt + 62, (int)s * c.steps, 1, __builtin_amdgcn_readfirstlane(tid / kWave),
                              NT / kWave};
-        const int cnt = c.sample ? clause_phase<true, kClust>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
+        const int cnt = c.sample ? clause_phase<true, kClust, kBucketPush>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
                                                               c.bnd, sc, tid, ps, c.key, c.nbh, c.full, c.lmask)
-                                 : clause_phase<false, kClust>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
+                                 : clause_phase<false, kClust, kBucketPush>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
                                                                c.bnd, sc, tid, ps, c.key, c.nbh, c.full, c.lmask);
         const int part = block_total(L, cnt, tid, NT);
         // publish the partial logits of the variables other members own
@@ -1410,7 +1464,7 @@ __global__ __launch_bounds__(1024) void sweep_split_kernel(SweepParams<Real> P, 
     c.vbuf = reinterpret_cast<uint32_t *>(Q.vbuf + (size_t)item * Q.nstride);
     c.pcnt = Q.cnt + (size_t)item * 2 * kMaxSplit;
 
-    load_push_tables<kBucketPush, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT);
+    load_push_tables<kBucketPush, kClust>(L, P.thr, P.gfx, P.gpad, tau, tid, NT, (1u << P.K) - 1u);
     for (int i = tid; i < N; i += NT) {
         L.v[i] = P.v[c.sbase + i];
         L.x[i] = 0;
