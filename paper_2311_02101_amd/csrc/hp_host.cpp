@@ -451,10 +451,11 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     p->threads = opts->threads;
 
     // --- kernel variant and size class per formula, work list, buckets ---
-    // kind: push (G tables in LDS) when everything fits, else push with the
-    // G tables in global memory, else the pull kernel.  Formulas are ordered
-    // by (kind, size class) and, inside a class, largest first; each (kind,
-    // class) run of work items becomes one launch.
+    // kind: push (tables in LDS) when everything fits, else push with the
+    // merged paddings (mid) or all contribution rows (wide) in global
+    // memory, else the pull kernel.  Formulas are ordered by (push or pull,
+    // size class) and, inside a class, largest first; each such run of work
+    // items becomes one launch.
     auto kind_of = [&](int f) -> int {
         int32_t vo, xo, ho;
         const bool fx_ok = fx_shift >= 40;
@@ -490,10 +491,17 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         }
         cls[f] = size_class(f);
     }
+    // Buckets: one per size class of the push family (the formulas of a class
+    // share a launch whatever table layout each would fit, so the chains of
+    // its largest and smallest formulas balance over one persistent grid;
+    // the bucket takes the layout its largest tables need: all in LDS, then
+    // mid, then wide), and one per size class of pull formulas.
+    auto pull_family = [&](int f) { return kind[f] == kBucketPull ? 1 : 0; };
+    auto layout_rank = [](int k) { return k == kBucketPush ? 0 : k == kBucketMid ? 1 : 2; };
     std::vector<int> order(F);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (kind[a] != kind[b]) return kind[a] < kind[b];
+        if (pull_family(a) != pull_family(b)) return pull_family(a) < pull_family(b);
         if (cls[a] != cls[b]) return cls[a] > cls[b];
         return (int64_t)fd[a].n * 7 + fd[a].c > (int64_t)fd[b].n * 7 + fd[b].c;
     });
@@ -501,13 +509,14 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     work.reserve((size_t)F * B);
     for (size_t j = 0; j < order.size(); ++j) {
         const int f = order[j];
-        if (j == 0 || kind[f] != kind[order[j - 1]] || cls[f] != cls[order[j - 1]]) {
+        if (j == 0 || pull_family(f) != pull_family(order[j - 1]) || cls[f] != cls[order[j - 1]]) {
             Bucket bk;
             bk.kind = kind[f];
             bk.first = (int32_t)work.size();
             p->buckets.push_back(bk);
         }
         Bucket &bk = p->buckets.back();
+        if (layout_rank(kind[f]) > layout_rank(bk.kind)) bk.kind = kind[f];
         bk.max_n = std::max(bk.max_n, fd[f].n);
         bk.max_c = std::max(bk.max_c, fd[f].c);
         for (int b = 0; b < B; ++b) work.push_back({f, b});
@@ -875,6 +884,31 @@ hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *st
         }
         bk = best_ms < 0.0f ? orig : best;
     }
+    // launch order of a run of several buckets: forked or in sequence, the
+    // faster of two timed runs each
+    if (e == hipSuccess && p->buckets.size() > 1) {
+        float best_ms = -1.0f;
+        int best_fork = p->forked;
+        const RunBuffers rb = plan_buffers(*p);
+        for (int fork = 1; fork >= 0 && e == hipSuccess; --fork) {
+            p->forked = fork;
+            float ms = -1.0f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = launch_buckets(*p, *st, n_sweeps, s, rb);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float m1 = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&m1, e0, e1);
+                if (e == hipSuccess && (ms < 0.0f || m1 < ms)) ms = m1;
+            }
+            if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best_fork = fork;
+            }
+        }
+        p->forked = best_fork;
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "hp_tune");
@@ -906,6 +940,7 @@ hp_status hp_plan_query(hp_plan_t plan, hp_plan_info *out) {
             out->bucket_dyn[i] = b.dyn;
         }
     }
+    out->forked = p->buckets.size() > 1 ? p->forked : 0;
     return HP_OK;
 }
 

@@ -215,6 +215,7 @@ struct Plan {
     int32_t xcd_map = 0;
     int64_t nstride = 0;
     int32_t use_graph = 0;
+    int32_t forked = 1;          // several buckets: forked over side streams (1) or in sequence (0)
     int32_t clust = 0;           // size-clustered model: tables in the clustered layout
     ClustRbm crbm = {};          // its RBMs (device copies in d_Wc / d_bc)
     double *d_Wc = nullptr;
@@ -282,6 +283,8 @@ void *static_scratch(int device);
 hipError_t launch_tables(const Plan &p, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb);
+// the launches of a run without the sweep-counter advance (the autotuner's trials)
+hipError_t launch_buckets(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb);
 // one bucket alone (no fork/join, no counter advance): used by the tuner
 hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s);
 // raise the dynamic-LDS limit of every sweep kernel to `bytes` (once per plan)

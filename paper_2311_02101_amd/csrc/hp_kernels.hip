@@ -1838,19 +1838,23 @@ hipError_t launch_split_t(const Plan &p, const hp_state &st, int64_t n_sweeps, h
 }
 
 // All launches of one run: a split launch, one bucket on the caller's
-// stream, or several buckets forked onto side streams (they are independent)
-// and joined back; then the sweep counter advances.
+// stream, or several buckets (they are independent) either forked onto side
+// streams and joined back, so that one bucket's tail overlaps the next, or in
+// sequence on the caller's stream (each persistent grid fills the GPU by
+// itself; the autotuner keeps the faster order); then the sweep counter
+// advances.
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s) {
     return launch_sweep(p, st, n_sweeps, s, plan_buffers(p));
 }
 
-hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb) {
+hipError_t launch_buckets(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb) {
     hipError_t e = hipSuccess;
     if (p.split > 1) {
         e = p.precision == HP_FP64 ? launch_split_t<double>(p, st, n_sweeps, s, rb)
                                    : launch_split_t<float>(p, st, n_sweeps, s, rb);
-    } else if (p.buckets.size() == 1) {
-        e = launch_bucket_q(p, p.buckets[0], st, n_sweeps, s, rb.queue);
+    } else if (p.buckets.size() == 1 || !p.forked) {
+        for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i)
+            e = launch_bucket_q(p, p.buckets[i], st, n_sweeps, s, rb.queue);
     } else {
         e = hipEventRecord(p.ev_fork, s);
         for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i) {
@@ -1860,6 +1864,11 @@ hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hip
         }
         for (size_t i = 0; i < p.buckets.size() && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, p.ev_join[i], 0);
     }
+    return e;
+}
+
+hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb) {
+    hipError_t e = launch_buckets(p, st, n_sweeps, s, rb);
     if (e != hipSuccess) return e;
     if (n_sweeps > 0) {
         advance_t_kernel<<<1, 64, 0, s>>>(st.t, n_sweeps);

@@ -63,11 +63,14 @@ __device__ __forceinline__ uint4 philox4x32_10_lane_key(uint4 x, Key2 key) {
 // word w, so in the first two rounds the products of the other words are the
 // same for every call of the sweep: round 1 maps the counter to
 // (hi(M1 w) ^ chain ^ k0, lo(M1 w), u2, u3) with u2 = hi(M0 tlo) ^ thi ^ k1
-// and u3 = lo(M0 tlo), and round 2 (key k + W) multiplies u2 by M1.
+// and u3 = lo(M0 tlo), and round 2 (key k + W) multiplies u2 by M1.  Word 1
+// after round 2, lo(M1 u2), is the same for every call too; round 3 only
+// XORs it with its key, so that XOR is done here (one scalar operand left
+// in the lane's three-input XOR, which takes at most one).
 struct PhiloxSweep {
     uint32_t c1;   // chain ^ k0
     uint32_t a2;   // hi(M1 u2) ^ (k0 + W0)
-    uint32_t b2;   // lo(M1 u2)
+    uint32_t b2k;  // lo(M1 u2) ^ (k0 + 2 W0)
     uint32_t d2;   // u3 ^ (k1 + W1)
 };
 
@@ -75,13 +78,14 @@ __device__ __forceinline__ PhiloxSweep philox_sweep_consts(uint32_t tlo, uint32_
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)tlo;
     const uint32_t u2 = (uint32_t)(p0 >> 32) ^ thi ^ key.k1;
     const uint64_t v = (uint64_t)0xCD9E8D57u * (uint64_t)u2;
-    return PhiloxSweep{chain ^ key.k0, (uint32_t)(v >> 32) ^ (key.k0 + 0x9E3779B9u), (uint32_t)v,
-                       (uint32_t)p0 ^ (key.k1 + 0xBB67AE85u)};
+    return PhiloxSweep{chain ^ key.k0, (uint32_t)(v >> 32) ^ (key.k0 + 0x9E3779B9u),
+                       (uint32_t)v ^ (key.k0 + 2u * 0x9E3779B9u), (uint32_t)p0 ^ (key.k1 + 0xBB67AE85u)};
 }
 
 // Philox4x32-10 of the counters (tlo, chain, w[i], thi) of one sweep: the
 // first two rounds from the sweep constants (5 lane instructions instead of
-// 8), then eight full rounds, the NS chains interleaved round by round.
+// 8), round 3 with a two-input XOR for word 0, then seven full rounds, the
+// NS chains interleaved round by round.
 template <int NS>
 __device__ __forceinline__ void philox_sweep_multi(uint4 (&x)[NS], const uint32_t (&w)[NS], const PhiloxSweep &u,
                                                    Key2 key) {
@@ -90,11 +94,18 @@ __device__ __forceinline__ void philox_sweep_multi(uint4 (&x)[NS], const uint32_
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)w[i];
         const uint32_t a = (uint32_t)(p1 >> 32) ^ u.c1;            // word 0 after round 1
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)a;
-        x[i] = make_uint4(u.a2 ^ (uint32_t)p1, u.b2, (uint32_t)(p0 >> 32) ^ u.d2, (uint32_t)p0);
+        x[i] = make_uint4(u.a2 ^ (uint32_t)p1, 0u, (uint32_t)(p0 >> 32) ^ u.d2, (uint32_t)p0);
     }
-    uint32_t k0 = key.k0 + 0x9E3779B9u, k1 = key.k1 + 0xBB67AE85u;   // round 2's key
+    uint32_t k0 = key.k0 + 2u * 0x9E3779B9u, k1 = key.k1 + 2u * 0xBB67AE85u;   // round 3's key
 #pragma unroll
-    for (int r = 2; r < 10; ++r) {
+    for (int i = 0; i < NS; ++i) {           // round 3: word 1 is lo(M1 u2), folded with k0 into b2k
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x[i].x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x[i].z;
+        x[i] = make_uint4((uint32_t)(p1 >> 32) ^ u.b2k, (uint32_t)p1,
+                          __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x[i].w, k1, 0x96), (uint32_t)p0);
+    }
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
         asm volatile("" : "+s"(k0), "+s"(k1));
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

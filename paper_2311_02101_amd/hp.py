@@ -55,7 +55,8 @@ class HpPlanInfo(ct.Structure):
                 ("lds_push", ct.c_int64), ("lds_pull", ct.c_int64),
                 ("bucket_kind", ct.c_int32 * 16), ("bucket_items", ct.c_int32 * 16),
                 ("bucket_threads", ct.c_int32 * 16), ("bucket_max_n", ct.c_int32 * 16),
-                ("bucket_grid", ct.c_int32 * 16), ("bucket_dyn", ct.c_int32 * 16)]
+                ("bucket_grid", ct.c_int32 * 16), ("bucket_dyn", ct.c_int32 * 16),
+                ("forked", ct.c_int32)]
 
 
 class HpState(ct.Structure):

@@ -545,6 +545,22 @@ def test_wide_tables_variant_against_oracle(hip):
     _trajectory(hip, tables, sizes, W, b, 2, 4, "f64", 9, label="wide tables")
 
 
+def test_size_class_shares_one_launch(hip):
+    """Formulas of one size class (8192 <= N < 16384) that would fit different
+    table layouts (all in LDS, mid, wide) share one launch in the layout the
+    largest needs, and match the oracle."""
+    from paper_2311_02101_amd import hp
+    sizes = [16000, 9000, 15000]
+    tables = [wl.random_formula(n, 21, tag=f) for f, n in enumerate(sizes)]
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    plan = hp.Plan(tables, sizes, W, b, chains=2, precision="f64", seed=21)
+    info = plan.info()
+    say(f"[one class] buckets {info['bucket_kind'][:info['n_buckets']]} max_n {info['bucket_max_n'][:info['n_buckets']]}")
+    assert info["n_buckets"] == 1 and info["bucket_kind"][0] == 1 and info["bucket_max_n"][0] == 16000
+    plan.free()
+    _trajectory(hip, tables, sizes, W, b, 2, 3, "f64", 21, label="one size class")
+
+
 def test_persistent_grid_matches_small_batch(hip):
     from paper_2311_02101_amd import hp
     n_f = 300
