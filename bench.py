@@ -182,14 +182,15 @@ def oracle_legs(w, cpu_sweeps, progress):
     """Time the oracle on a bounded sample of the workload, single-core and
     on all cores, and record teacher-forcing snapshots for the GPU parity
     check.  Single formula: all chains x cpu_sweeps sweeps; batches: 16
-    formulas spread over the sizes x 16 chains x 3 sweeps.  Returns the
-    timing summary and the snapshots."""
+    formulas spread over the sizes x all chains x 5 sweeps (about 25 s on
+    one core for the 1024-formula batch).  Returns the timing summary and the
+    snapshots."""
     batch = len(w.n_vars) > 1
     if batch:
         order = np.argsort(w.n_vars, kind="stable")
         pick = sorted({int(order[i]) for i in np.linspace(0, len(order) - 1, 16).astype(int)})
-        chains = np.arange(0, w.chains, max(1, w.chains // 16))
-        sweeps = 3
+        chains = np.arange(w.chains)
+        sweeps = 5
         par_chains = np.array(sorted({0, w.chains // 2 - 1, w.chains // 2, w.chains - 1}))
     else:
         pick, chains, sweeps = [0], np.arange(w.chains), cpu_sweeps
@@ -270,7 +271,7 @@ def main(argv=None):
     ap.add_argument("--split", type=int, default=0, help="workgroups per chain (0 = automatic)")
     ap.add_argument("--cpu-sweeps", type=int, default=25,
                     help="oracle sample sweeps on a single formula (all chains; about 13 s of CPU work on "
-                         "plain_n4096_b64); batches use 3 sweeps of 16 chains of 16 formulas; 0 skips the "
+                         "plain_n4096_b64); batches use 5 sweeps of all chains of 16 formulas; 0 skips the "
                          "CPU legs and the parity check")
     ap.add_argument("--graph", type=int, default=-1, help="hipGraph replay (default: on for batches)")
     ap.add_argument("--tune", type=int, default=-1, help="autotune first (default: on for batches)")
@@ -390,7 +391,11 @@ def main(argv=None):
     kernel_name = ("sweep_pull_kernel" if args.kernel == "pull" else
                    "sweep_split_kernel" if plan.split > 1 else "sweep_push_kernel")
     info = plan.info()
-    tkey = ",".join(str(t) for t in info["bucket_threads"]) if batch else str(info["bucket_threads"][0])
+    # the tuner's shapes vary a little from run to run (timing noise), so a
+    # tuned batch's counters are keyed by "tuned"
+    tuned = (args.tune if args.tune >= 0 else int(batch)) == 1
+    tkey = "tuned" if tuned else ",".join(str(t) for t in info["bucket_threads"]) if batch else \
+        str(info["bucket_threads"][0])
     traffic = measured_traffic(kernel_name, args.workload, precision, plan.split, tkey)
     N = w.n_vars[0] if not batch else int(sum(w.n_vars))
     C = w.tables[0].shape[1] if not batch else int(sum(t.shape[1] for t in w.tables))
@@ -403,7 +408,7 @@ def main(argv=None):
         "config": {"workload": args.workload, "formulas": len(w.n_vars), "model": args.model,
                    "n_vars": N, "clauses": C, "K": 7, "L": L if not clustered else "3 or len + 1",
                    "chains": B, "sweeps_per_step": args.sweeps, "temperatures": list(wl.FSTAR_PAIR),
-                   "graph": use_graph, "tuned": (args.tune if args.tune >= 0 else int(batch)) == 1,
+                   "graph": use_graph, "tuned": tuned,
                    "threads": args.threads or "automatic", "kernel": args.kernel,
                    "launch": info, "parallelism": "single GPU"},
         "chain_sweeps_per_s": B * args.sweeps * instances / wall,

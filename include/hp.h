@@ -207,10 +207,8 @@ hp_status hp_run_noalloc(hp_plan_t plan, const hp_state *state, int64_t n_sweeps
  * workgroup size (64..1024) and, for the push kernels of the padded model in
  * FP64/FP32, the table layout: every table in LDS, the merged padding table
  * in global memory, or both contribution tables in global memory (smaller
- * LDS footprints let more workgroups share a CU).  Then, for a plan of
- * several launches, it times a whole run with the launches forked over side
- * streams and with them in sequence on the caller's stream, and keeps the
- * faster order.  All shapes and orders compute the same bits.  The trial runs overwrite the state's v, nu, s_max and best
+ * LDS footprints let more workgroups share a CU).  All shapes compute the
+ * same bits.  The trial runs overwrite the state's v, nu, s_max and best
  * without advancing t, so pass a scratch state of the right shape.
  * Synchronous.  Cached graphs are discarded. */
 hp_status hp_tune(hp_plan_t plan, const hp_state *scratch, int64_t n_sweeps, void *stream);
@@ -231,8 +229,11 @@ typedef struct {
      * (1) or dealt round-robin (0) */
     int32_t bucket_kind[16], bucket_items[16], bucket_threads[16], bucket_max_n[16], bucket_grid[16];
     int32_t bucket_dyn[16];
-    int32_t forked;                 /* 1: a run's launches forked over side streams
-                                       (the default), 0: in sequence on the caller's  */
+    int32_t forked;                 /* a plan of several launches: 1 = forked over side
+                                       streams (some launch has one workgroup per item
+                                       and may leave CUs free), 0 = in sequence on the
+                                       caller's stream (every launch a persistent grid
+                                       that fills the GPU)                            */
 } hp_plan_info;
 
 /* Fill *out with the plan's launch configuration.  HP_EINVAL on NULL. */

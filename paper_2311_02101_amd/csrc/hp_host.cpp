@@ -205,6 +205,20 @@ const char *hp_status_string(hp_status s) {
 
 const char *hp_last_error(void) { return g_last_error.c_str(); }
 
+// Launch order of a run of several buckets.  Each persistent grid fills the
+// GPU by itself, and when every launch is one they run best in sequence on
+// the caller's stream (1885 against 1920 ms for the 500-sweep run of the
+// 1024-formula batch: kernels resident side by side compete for the CUs);
+// a launch of one workgroup per item may leave CUs free, and then the
+// launches are forked over side streams to run side by side.  (Timing the
+// two orders on the autotuner's short trials favours forking, which hides
+// the per-item setup that dominates a run of a few sweeps.)
+static void choose_order(Plan *p) {
+    p->forked = 0;
+    for (const Bucket &b : p->buckets)
+        if (b.grid == 0) p->forked = 1;
+}
+
 hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp_opts *opts,
                   void *stream) {
     g_last_error.clear();
@@ -574,6 +588,7 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
         const int64_t capacity = (int64_t)p->cus * std::max(occ, 1);
         bk.grid = (bk.kind != kBucketPull && bk.count > capacity) ? (int32_t)capacity : 0;
     }
+    choose_order(p);
 
     // --- split: G co-resident workgroups per chain, single push bucket only ---
     int G = 1;
@@ -884,31 +899,7 @@ hp_status hp_tune(hp_plan_t plan, const hp_state *st, int64_t n_sweeps, void *st
         }
         bk = best_ms < 0.0f ? orig : best;
     }
-    // launch order of a run of several buckets: forked or in sequence, the
-    // faster of two timed runs each
-    if (e == hipSuccess && p->buckets.size() > 1) {
-        float best_ms = -1.0f;
-        int best_fork = p->forked;
-        const RunBuffers rb = plan_buffers(*p);
-        for (int fork = 1; fork >= 0 && e == hipSuccess; --fork) {
-            p->forked = fork;
-            float ms = -1.0f;
-            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-                e = hipEventRecord(e0, s);
-                if (e == hipSuccess) e = launch_buckets(*p, *st, n_sweeps, s, rb);
-                if (e == hipSuccess) e = hipEventRecord(e1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float m1 = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&m1, e0, e1);
-                if (e == hipSuccess && (ms < 0.0f || m1 < ms)) ms = m1;
-            }
-            if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
-                best_ms = ms;
-                best_fork = fork;
-            }
-        }
-        p->forked = best_fork;
-    }
+    choose_order(p);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "hp_tune");

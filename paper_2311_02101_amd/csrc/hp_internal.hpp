@@ -283,7 +283,7 @@ void *static_scratch(int device);
 hipError_t launch_tables(const Plan &p, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s);
 hipError_t launch_sweep(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb);
-// the launches of a run without the sweep-counter advance (the autotuner's trials)
+// the launches of a run without the sweep-counter advance
 hipError_t launch_buckets(const Plan &p, const hp_state &st, int64_t n_sweeps, hipStream_t s, const RunBuffers &rb);
 // one bucket alone (no fork/join, no counter advance): used by the tuner
 hipError_t launch_bucket(const Plan &p, const Bucket &b, const hp_state &st, int64_t n_sweeps, hipStream_t s);
