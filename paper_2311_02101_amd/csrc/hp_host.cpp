@@ -93,13 +93,12 @@ void release(Plan *p) {
 
 
 // Variable groups (of 4) per thread whose variance EMA stays in registers:
-// 1, 2 or 4 (FP32), else 0 (EMA in global memory).  The mixed-precision
-// kernel and the FP64 kernels keep at most one group in registers (two
-// spill: the FP64 push kernel measured 1.2% faster with the EMA of two groups
-// in global memory).
+// 1, 2 (FP32 and FP64) or 4 (FP32), else 0 (EMA in global memory).  The
+// mixed-precision kernel keeps at most one group in registers (two spill
+// next to its MFMA operands); four FP64 groups spill.
 int vpt_for(int groups, int threads, bool mixed, bool fp64) {
     if (groups <= threads) return 1;
-    if (groups <= 2 * threads && !mixed && !fp64) return 2;
+    if (groups <= 2 * threads && !mixed) return 2;
     if (groups <= 4 * threads && !mixed && !fp64) return 4;
     return 0;
 }
