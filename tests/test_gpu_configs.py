@@ -52,6 +52,8 @@ def test_uneven_1024x64_fp32_graph_tuned_sampled_formulas(hip, uneven_workload):
     info = plan.info()
     say(f"[uneven 1024x64] {info['n_buckets']} launches, threads {info['bucket_threads'][:info['n_buckets']]}")
     assert info["n_buckets"] > 1 and info["split"] == 1
+    # every launch a persistent grid: in sequence on the caller's stream
+    assert all(g > 0 for g in info["bucket_grid"]) and info["forked"] == 0
     st = plan.new_state(w.v0)
     plan.run(st, 20)                      # away from the initial states, through the graph
     _sync()

@@ -596,6 +596,8 @@ def test_graph_replays_match_eager(hip):
     v0 = [wl.initial_state(8, n, 14, tag=f) for f, n in enumerate(sizes)]
     eager = hp.Plan(tables, sizes, W, b, chains=8, precision="f64", seed=14)
     graph = hp.Plan(tables, sizes, W, b, chains=8, precision="f64", seed=14, graph=True)
+    # four launches of one workgroup per item: forked over side streams
+    assert graph.info()["n_buckets"] == 4 and graph.info()["forked"] == 1
     se, sg = eager.new_state(v0), graph.new_state(v0)
     junk = torch.zeros(1 << 20, device="cuda")
     for rep in range(4):
