@@ -204,11 +204,12 @@ hp_status hp_run_noalloc(hp_plan_t plan, const hp_state *state, int64_t n_sweeps
 
 /* Autotuner: for every launch of the plan, time each candidate shape on
  * `n_sweeps` sweeps of the given state and keep the fastest.  A shape is a
- * workgroup size (64..1024) and, for the push kernels of the padded model in
- * FP64/FP32, the table layout: every table in LDS, the merged padding table
- * in global memory, or both contribution tables in global memory (smaller
- * LDS footprints let more workgroups share a CU).  All shapes compute the
- * same bits.  The trial runs overwrite the state's v, nu, s_max and best
+ * workgroup size (64..1024), for the push kernels of the padded model in
+ * FP64/FP32 the table layout (every table in LDS, the merged-padding words
+ * of the contribution rows in global memory, or all contribution rows in
+ * global memory: smaller LDS footprints let more workgroups share a CU), and
+ * how a chain's waves share its clause steps (from a counter or dealt
+ * round-robin).  All shapes compute the same bits.  The trial runs overwrite the state's v, nu, s_max and best
  * without advancing t, so pass a scratch state of the right shape.
  * Synchronous.  Cached graphs are discarded. */
 hp_status hp_tune(hp_plan_t plan, const hp_state *scratch, int64_t n_sweeps, void *stream);
@@ -222,8 +223,8 @@ typedef struct {
     int32_t fx_shift;               /* S: push accumulators count units of 2^-S       */
     int32_t n_buckets;              /* launches per run (one per size class/variant)  */
     int64_t lds_push, lds_pull;     /* largest dynamic LDS bytes per workgroup        */
-    /* first 16 launches: variant (0 push, 1 push with both contribution
-     * tables in global memory, 2 pull, 3 push with the padding table in
+    /* first 16 launches: variant (0 push, 1 push with the contribution rows
+     * in global memory, 2 pull, 3 push with the merged-padding words in
      * global memory), work items, workgroup size, largest N, persistent grid
      * (0 = one workgroup per item), clause-phase steps taken from a counter
      * (1) or dealt round-robin (0) */
