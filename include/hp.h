@@ -221,7 +221,8 @@ typedef struct {
     int32_t push_items;             /* (formula, chain) items on the push kernels     */
     int32_t pull_items;             /* (formula, chain) items on the pull kernel      */
     int32_t fx_shift;               /* S: push accumulators count units of 2^-S       */
-    int32_t n_buckets;              /* launches per run (one per size class/variant)  */
+    int32_t n_buckets;              /* launches per run (one per size class, push and
+                                       pull formulas apart)                           */
     int64_t lds_push, lds_pull;     /* largest dynamic LDS bytes per workgroup        */
     /* first 16 launches: variant (0 push, 1 push with the contribution rows
      * in global memory, 2 pull, 3 push with the merged-padding words in
