@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kFeThreads) void free_energy_kernel(const FormulaDe
         if (lane == 0) s_part[wave][t] = x;
     }
     __syncthreads();
-    if (threadIdx.x < T) {
+    if ((int)threadIdx.x < T) {
         double x = 0.0;
         for (int i = 0; i < (int)blockDim.x / kWave; ++i) x += s_part[i][threadIdx.x];
         out[(size_t)blockIdx.x * T + threadIdx.x] = x;
