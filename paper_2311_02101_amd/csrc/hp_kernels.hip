@@ -3,7 +3,9 @@
 // One workgroup advances one chain of one formula through all requested
 // sweeps; the chain's state stays on chip for the whole launch (v in LDS, the
 // variance EMA in registers), so HBM/L2 traffic per sweep is only the shared
-// clause data of the formula (the same for every chain, hence L2-resident).
+// clause data of the formula and, in the wide and mid table layouts, the
+// contribution rows of the chain's temperature (the same for every chain of
+// the formula, hence L2-resident).
 //
 // Two variants of the scatter-add of eq. 7:
 //   push (default) -- right after a clause's hidden units are drawn, its
