@@ -676,6 +676,12 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
     HP_TRY(upload(&p->d_lits, lits, s), "upload clause table");
     HP_TRY(upload(&p->d_csr_ptr, csr_ptr, s), "upload occurrence offsets");
     HP_TRY(upload(&p->d_occ, occ, s), "upload occurrences");
+    // one step of zero records past the last formula's: a wave's last step of
+    // a length run loads all 64 lanes' records (the lanes past the run are
+    // masked), and the step's offset travels in the loads' scalar offset,
+    // which the descriptor's range check does not cover
+    rec.resize((size_t)NC + kWave);
+    orig.resize((size_t)NC + kWave);
     HP_TRY(upload(&p->d_rec, rec, s), "upload clause records");
     HP_TRY(upload(&p->d_orig, orig, s), "upload clause order");
     HP_TRY(upload(&p->d_negcnt, negcnt, s), "upload negation counts");

@@ -657,9 +657,11 @@ __device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint
 }
 
 // A wave's view of a range of clause records: raw buffer descriptors over
-// the records and their first hidden-draw blocks (loads past the range
-// return zeros), so a load of 64 consecutive records takes a wave-uniform byte offset in a
-// scalar register and the lane's fixed offset in a vector register.
+// the records and their first hidden-draw blocks, so a load of 64
+// consecutive records takes a wave-uniform byte offset in a scalar register
+// and the lane's fixed offset in a vector register.  The lanes of a run's
+// last step that lie past the run load the next records (or the zero
+// records after the last formula's) and are masked.
 struct RecView {
     __amdgpu_buffer_rsrc_t rec, orig;
 };
