@@ -1,9 +1,10 @@
 """Property-based GPU parity on tiny random formulas (Hypothesis, derandomized):
 for any formula of 1..40 variables and 1..80 clauses of width 1..7, random
 N(0,1) OR-gate weights, 1..6 chains over two temperatures and 0..8 sweeps,
-the HIP path (push or pull kernel, FP64) ends in the oracle's state: v,
-s_max and best exactly, nu within the FP64 class (a differing visible draw
-must be a tie of the plan's bound, replayed with teacher forcing).
+the HIP path (push or pull kernel, FP64 or FP32) ends in the oracle's state:
+v, s_max and best exactly, nu within the precision's class (a differing
+visible draw must be a tie of the class's bound, replayed with teacher
+forcing).
 
 Every example prints its sizes and seed before touching the GPU."""
 import numpy as np
@@ -32,10 +33,10 @@ def formulas(draw):
     return n, k, clauses
 
 
-@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+@settings(max_examples=60, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
 @given(formulas(), st.integers(0, 2 ** 31 - 1), st.integers(1, 6), st.integers(0, 8),
-       st.sampled_from(["push", "pull"]))
-def test_random_tiny_formulas_match_oracle(hip, f, seed, chains, sweeps, kernel):
+       st.sampled_from(["push", "pull"]), st.sampled_from(["f64", "f32"]))
+def test_random_tiny_formulas_match_oracle(hip, f, seed, chains, sweeps, kernel, prec):
     from paper_2311_02101_amd import hp
     n, k, clauses = f
     T = wl.pad_clauses(clauses, k)
@@ -43,21 +44,21 @@ def test_random_tiny_formulas_match_oracle(hip, f, seed, chains, sweeps, kernel)
     rng = np.random.default_rng(seed)
     W, b = rng.standard_normal((2, k, L)), rng.standard_normal((2, L))
     temps = wl.default_temperatures(chains, 2)
-    say(f"[property] N={n} C={len(clauses)} K={k} L={L} B={chains} S={sweeps} {kernel} seed={seed}")
-    plan = hp.Plan([T], [n], W, b, chains=chains, temps=temps, precision="f64", seed=seed, kernel=kernel)
-    tie, nu_rtol = f64_bounds(plan, [T])
+    say(f"[property] N={n} C={len(clauses)} K={k} L={L} B={chains} S={sweeps} {kernel} {prec} seed={seed}")
+    plan = hp.Plan([T], [n], W, b, chains=chains, temps=temps, precision=prec, seed=seed, kernel=kernel)
+    tie, nu_rtol = f64_bounds(plan, [T]) if prec == "f64" else (None, None)
     v0 = wl.initial_state(chains, n, seed % 1000)
     st_ = plan.new_state([v0])
     plan.run(st_, sweeps)
     op = R.plan(T, n, W, b)
     ost = R.run(R.initial(v0), op, temps, sweeps, alpha=1e-3, seed=seed)
     try:
-        compare_state(st_.formula(0), (ost.v, ost.nu, ost.s_max, ost.best), "f64", "property", nu_rtol=nu_rtol)
+        compare_state(st_.formula(0), (ost.v, ost.nu, ost.s_max, ost.best), prec, "property", nu_rtol=nu_rtol)
     except AssertionError:
         # every differing draw must be a tie: replay sweep by sweep
         s2 = plan.new_state([v0])
         o2 = R.initial(v0)
-        ties = sum(teacher_forced_sweep(plan, s2, 0, o2, op, temps, alpha=1e-3, seed=seed, prec="f64",
+        ties = sum(teacher_forced_sweep(plan, s2, 0, o2, op, temps, alpha=1e-3, seed=seed, prec=prec,
                                         tie=tie, nu_rtol=nu_rtol) for _ in range(sweeps))
         assert ties > 0
     plan.free()
