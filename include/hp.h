@@ -286,6 +286,8 @@ const char *hp_last_error(void);
 #define HP_MLP_HIDDEN 256
 /* parameter vector: W1 [32][256] | b1 [256] | w2 [256] | b2 [1] */
 #define HP_MLP_PARAMS (HP_MLP_IN * HP_MLP_HIDDEN + 2 * HP_MLP_HIDDEN + 1)
+/* rows of the backward pass's partial-sum workspace (one per workgroup) */
+#define HP_MLP_PARTS 1024
 
 typedef struct {                    /* caller-owned DEVICE buffers                     */
     float *params;                  /* [HP_MLP_PARAMS] FP32 master parameters          */
@@ -294,6 +296,8 @@ typedef struct {                    /* caller-owned DEVICE buffers              
     uint16_t *w_bf16;               /* [32*256 + 256] bfloat16 copies: W1 transposed
                                        ([256][32]) then w2; refreshed by
                                        hp_mlp_sync and hp_mlp_adam                     */
+    float *partials;                /* [HP_MLP_PARTS][HP_MLP_PARAMS + 1] workspace of
+                                       hp_mlp_backward (its contents are scratch)      */
 } hp_mlp;
 
 /* Per-variable features of every formula of the plan, as bfloat16
@@ -309,7 +313,11 @@ hp_status hp_mlp_sync(const hp_mlp *net, void *stream);
 hp_status hp_mlp_forward(const hp_mlp *net, const uint16_t *x, int64_t rows, float *q, void *stream);
 
 /* net->grad = gradient of the mean binary cross-entropy of q against the
- * labels y in [0,1]; *loss_sum (device float) = the summed loss. */
+ * labels y in [0,1]; *loss_sum (device float) = the summed loss.  Each
+ * workgroup writes the sums of its rows to its row of net->partials, and a
+ * second kernel adds the rows up in a fixed order: for a given input the
+ * gradient and the loss are the same bits on every call (no atomics).
+ * Calls that share one partials buffer must not overlap. */
 hp_status hp_mlp_backward(const hp_mlp *net, const uint16_t *x, const float *y, int64_t rows,
                           float *loss_sum, void *stream);
 

@@ -998,7 +998,7 @@ hp_status hp_mlp_forward(const hp_mlp *net, const uint16_t *x, int64_t rows, flo
 hp_status hp_mlp_backward(const hp_mlp *net, const uint16_t *x, const float *y, int64_t rows, float *loss_sum,
                           void *stream) {
     g_last_error.clear();
-    if (!mlp_ok(net) || !x || !y || !loss_sum) return fail(HP_EINVAL, "null argument");
+    if (!mlp_ok(net) || !net->partials || !x || !y || !loss_sum) return fail(HP_EINVAL, "null argument");
     if (rows < 1) return fail(HP_EINVAL, "rows must be >= 1");
     hipError_t e = launch_mlp(*net, x, y, rows, nullptr, loss_sum, true, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "mlp backward");

@@ -1,6 +1,7 @@
 // Learned initial assignments: per-variable features, a 32 -> 256 -> 1
 // perceptron (bfloat16 weights on MFMA, FP32 accumulation) with its training
-// kernels (forward + backward fused, Adam), and the initial Bernoulli draws.
+// kernels (backward with the forward recomputed, a fixed-order reduction of
+// its partial sums, Adam), and the initial Bernoulli draws.
 //
 // Features (per variable, exact dyadic values before one bfloat16 rounding):
 //   0..13  clauses of real length l = 1..7 holding the variable positively
@@ -82,151 +83,267 @@ __global__ void feature_finish_kernel(const float *__restrict__ acc, int64_t nv,
     }
 }
 
-// ---- perceptron: forward (+ backward) ------------------------------------------
+// ---- perceptron: forward -------------------------------------------------------
 // One wave per 32-row tile (waves stride over the tiles).  Hidden layer on
 // MFMA 32x32x16 bf16: lane l holds rows/columns as
 //   A[32 x 16]: row l%32, k = (l/32)*8 + 0..7;  B[16 x 32]: column l%32, same k;
 //   D[32 x 32]: register i -> row (i/4)*8 + (l/32)*4 + i%4, column l%32.
-// The backward product dW1 = x^T dh reuses each lane's own D registers as the
-// B operand by ordering its reduction index (the rows) as the D layout does:
-// step s, k = (l/32)*8 + m  <->  row ((s*8 + m)/4)*8 + (l/32)*4 + m%4.
 constexpr int kWaves = 4;
 
-template <bool kBackward>
-__global__ __launch_bounds__(kWaves * 64) void mlp_kernel(const uint16_t *__restrict__ x, const float *__restrict__ y,
-                                                          int64_t rows, const float *__restrict__ params,
-                                                          const uint16_t *__restrict__ wbf, float *__restrict__ q_out,
-                                                          float *__restrict__ grad, float *__restrict__ loss_sum) {
-    __shared__ __align__(16) uint16_t s_w1t[kH * kF];          // W1 transposed: [column][feature]
-    __shared__ float s_b1[kH], s_w2[kH];
-    __shared__ __align__(16) uint16_t s_xt[kWaves][kF * 32];   // x tile transposed: [feature][row]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < kH * kF; i += blockDim.x) s_w1t[i] = wbf[i];
-    for (int i = tid; i < kH; i += blockDim.x) {
+// row of D register i for lane half h (see above)
+__device__ __forceinline__ int d_row(int i, int h) { return (i / 4) * 8 + h * 4 + (i % 4); }
+
+// W1 (transposed bfloat16), b1 and w2 of the network into LDS
+__device__ __forceinline__ void load_weights(const float *params, const uint16_t *wbf, uint16_t *s_w1t, float *s_b1,
+                                             float *s_w2, int tid) {
+    for (int i = tid; i < kH * kF; i += kWaves * 64) s_w1t[i] = wbf[i];
+    for (int i = tid; i < kH; i += kWaves * 64) {
         s_b1[i] = params[kOffB1 + i];
         s_w2[i] = bf16_value(wbf[kH * kF + i]);
     }
+}
+
+// The two A operands (k-steps) of the 32-row tile starting at row0: lane l
+// takes row row0 + l%32, features (l/32)*8 + 0..7 and 16 + (l/32)*8 + 0..7
+// (zeros past the last row).  Operands move as integer words: element m of a
+// bfloat16 vector is bits 16*(m%2) of word m/2.
+__device__ __forceinline__ void load_x_tile(const uint16_t *x, int64_t rows, int64_t row0, int lane, uint4 &x0,
+                                            uint4 &x1) {
+    const int64_t r = row0 + (lane & 31);
+    const int half = lane >> 5;
+    x0 = make_uint4(0, 0, 0, 0);
+    x1 = make_uint4(0, 0, 0, 0);
+    if (r < rows) {
+        x0 = *reinterpret_cast<const uint4 *>(x + r * kF + half * 8);
+        x1 = *reinterpret_cast<const uint4 *>(x + r * kF + 16 + half * 8);
+    }
+}
+
+// pre-activations of hidden columns [32 j, 32 j + 32) for the tile's rows
+__device__ __forceinline__ f32x16 hidden_chunk(const uint16_t *s_w1t, int j, int lane, bf16x8 a0, bf16x8 a1) {
+    const int col = j * 32 + (lane & 31), half = lane >> 5;
+    const bf16x8 bw0 = *reinterpret_cast<const bf16x8 *>(s_w1t + col * kF + half * 8);
+    const bf16x8 bw1 = *reinterpret_cast<const bf16x8 *>(s_w1t + col * kF + 16 + half * 8);
+    f32x16 acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw1, acc, 0, 0, 0);
+    return acc;
+}
+
+// output logits w2 . relu(W1^T x + b1) of the tile's rows, without b2: after
+// the butterfly every lane of half h holds s[i] for row d_row(i, h)
+__device__ __forceinline__ void tile_logits(const uint16_t *s_w1t, const float *s_b1, const float *s_w2, int lane,
+                                            bf16x8 a0, bf16x8 a1, float (&s)[16]) {
+    for (int i = 0; i < 16; ++i) s[i] = 0.0f;
+    // not unrolled: the unrolled loop hoists every chunk's operand loads and
+    // needs twice the registers (half the resident waves) for no gain
+#pragma unroll 1
+    for (int j = 0; j < 8; ++j) {
+        const f32x16 acc = hidden_chunk(s_w1t, j, lane, a0, a1);
+        const int col = j * 32 + (lane & 31);
+        const float bb = s_b1[col], ww = s_w2[col];
+        for (int i = 0; i < 16; ++i) s[i] += fmaxf(acc[i] + bb, 0.0f) * ww;
+    }
+    for (int off = 1; off < 32; off <<= 1)
+        for (int i = 0; i < 16; ++i) s[i] += __shfl_xor(s[i], off, 64);
+}
+
+__global__ __launch_bounds__(kWaves * 64) void mlp_forward_kernel(const uint16_t *__restrict__ x, int64_t rows,
+                                                                  const float *__restrict__ params,
+                                                                  const uint16_t *__restrict__ wbf,
+                                                                  float *__restrict__ q_out) {
+    __shared__ __align__(16) uint16_t s_w1t[kH * kF];          // W1 transposed: [column][feature]
+    __shared__ float s_b1[kH], s_w2[kH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    load_weights(params, wbf, s_w1t, s_b1, s_w2, tid);
+    __syncthreads();
+    const float b2 = params[kOffB2];
+    const int half = lane >> 5, col_in = lane & 31;
+    const int64_t n_tiles = (rows + 31) / 32;
+    for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < n_tiles; tile += (int64_t)gridDim.x * kWaves) {
+        uint4 x0, x1;
+        load_x_tile(x, rows, tile * 32, lane, x0, x1);
+        float s[16];
+        tile_logits(s_w1t, s_b1, s_w2, lane, __builtin_bit_cast(bf16x8, x0), __builtin_bit_cast(bf16x8, x1), s);
+        if (col_in == 0)
+            for (int i = 0; i < 16; ++i) {
+                const int64_t r = tile * 32 + d_row(i, half);
+                if (r < rows) q_out[r] = 1.0f / (1.0f + expf(-(s[i] + b2)));
+            }
+    }
+}
+
+// ---- perceptron: backward --------------------------------------------------------
+// A workgroup of 4 waves takes 128 rows per step, as 4 tiles of 32.
+//   pass 1: wave w computes the logits of tile w (all 256 hidden columns, as
+//           the forward kernel); lanes 0..31 then take one row each for q, the
+//           output gradient g = (q - y) / rows and the loss; tile w's rows (row
+//           major and transposed) and g go to LDS;
+//   pass 2: wave w owns hidden columns [64 w, 64 w + 64) (two MFMA column
+//           chunks): for each of the 4 tiles it recomputes their
+//           pre-activations, forms dh = g w2 relu'(pre) (bfloat16 for the
+//           product) and adds x^T dh to its dW1 chunks, g h to dw2 and dh to db1.
+// Each dW1 column is accumulated by one wave only: a wave keeps 2 chunks of
+// accumulators instead of all 8 (the register file then holds several waves
+// per SIMD), and the workgroup's row of the workspace needs a cross-wave sum
+// for b2 and the loss only.  The x^T dh product reuses the D layout as its B
+// operand by ordering the reduction index (the rows) as D does:
+// step s, k = (l/32)*8 + m  <->  row ((s*8 + m)/4)*8 + (l/32)*4 + m%4.
+// (3 waves per SIMD: the register budget of 170 holds pass 2 without spills;
+// the compiler's own choice, 2 waves, ran 8% slower)
+__global__ __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3))) void mlp_backward_kernel(const uint16_t *__restrict__ x,
+                                                                   const float *__restrict__ y, int64_t rows,
+                                                                   const float *__restrict__ params,
+                                                                   const uint16_t *__restrict__ wbf,
+                                                                   float *__restrict__ part) {
+    __shared__ __align__(16) uint16_t s_w1t[kH * kF];
+    __shared__ float s_b1[kH], s_w2[kH];
+    __shared__ __align__(16) uint16_t s_x[kWaves][32 * kF];   // tile rows: [row][feature]
+    __shared__ __align__(16) uint16_t s_xt[kWaves][kF * 32];  // transposed: [feature][row]
+    __shared__ __align__(16) float s_o[kWaves][32];           // logits, then g
+    __shared__ float s_red[kWaves][2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    load_weights(params, wbf, s_w1t, s_b1, s_w2, tid);
     __syncthreads();
     const float b2 = params[kOffB2];
     const float inv_rows = 1.0f / (float)rows;
     const int half = lane >> 5, col_in = lane & 31;
-    const int64_t n_tiles = (rows + 31) / 32;
-    f32x16 dw1[8];
-    float dw2[8], db1[8];
-    for (int j = 0; j < 8; ++j) {
-        dw1[j] = f32x16{};
-        dw2[j] = 0.0f;
-        db1[j] = 0.0f;
-    }
-    float db2 = 0.0f, lsum = 0.0f;
+    const int64_t n_steps = (rows + 127) / 128;
+    f32x16 dw1[2] = {f32x16{}, f32x16{}};
+    float dw2[2] = {0.0f, 0.0f}, db1[2] = {0.0f, 0.0f};
+    float db2 = 0.0f, lsum = 0.0f;                // lanes 0..31: their rows' sums
 
-    for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < n_tiles; tile += (int64_t)gridDim.x * kWaves) {
-        // ---- load the x tile (A operands of the two k-steps) ----
-        // operands move as integer words: element m of a bfloat16 vector is
-        // bits 16*(m%2) of word m/2
-        const int64_t row_a = tile * 32 + col_in;
-        uint4 x0 = make_uint4(0, 0, 0, 0), x1 = make_uint4(0, 0, 0, 0);
-        if (row_a < rows) {
-            x0 = *reinterpret_cast<const uint4 *>(x + row_a * kF + half * 8);
-            x1 = *reinterpret_cast<const uint4 *>(x + row_a * kF + 16 + half * 8);
-        }
-        const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
-        if (kBackward) {
+    for (int64_t step = blockIdx.x; step < n_steps; step += gridDim.x) {   // uniform over the workgroup
+        // ---- pass 1: tile `wave` ----
+        const int64_t row0 = (step * kWaves + wave) * 32;
+        uint4 x0, x1;
+        load_x_tile(x, rows, row0, lane, x0, x1);
+        *reinterpret_cast<uint4 *>(&s_x[wave][col_in * kF + half * 8]) = x0;
+        *reinterpret_cast<uint4 *>(&s_x[wave][col_in * kF + 16 + half * 8]) = x1;
+        {
             const uint32_t w0[4] = {x0.x, x0.y, x0.z, x0.w}, w1[4] = {x1.x, x1.y, x1.z, x1.w};
             for (int m = 0; m < 8; ++m) {
                 s_xt[wave][(half * 8 + m) * 32 + col_in] = (uint16_t)(w0[m >> 1] >> (16 * (m & 1)));
                 s_xt[wave][(16 + half * 8 + m) * 32 + col_in] = (uint16_t)(w1[m >> 1] >> (16 * (m & 1)));
             }
         }
-        // ---- pass 1: output logit of every row ----
         float s[16];
-        for (int i = 0; i < 16; ++i) s[i] = 0.0f;
-        for (int j = 0; j < 8; ++j) {
-            const int col = j * 32 + col_in;
-            const bf16x8 bw0 = *reinterpret_cast<const bf16x8 *>(s_w1t + col * kF + half * 8);
-            const bf16x8 bw1 = *reinterpret_cast<const bf16x8 *>(s_w1t + col * kF + 16 + half * 8);
-            f32x16 acc = {};
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw1, acc, 0, 0, 0);
-            const float bb = s_b1[col], ww = s_w2[col];
-            for (int i = 0; i < 16; ++i) s[i] += fmaxf(acc[i] + bb, 0.0f) * ww;
+        tile_logits(s_w1t, s_b1, s_w2, lane, __builtin_bit_cast(bf16x8, x0), __builtin_bit_cast(bf16x8, x1), s);
+        if (col_in == 0)
+            for (int q4 = 0; q4 < 4; ++q4)
+                *reinterpret_cast<float4 *>(&s_o[wave][q4 * 8 + half * 4]) =
+                    make_float4(s[4 * q4] + b2, s[4 * q4 + 1] + b2, s[4 * q4 + 2] + b2, s[4 * q4 + 3] + b2);
+        __syncthreads();
+        if (lane < 32) {
+            const int64_t r = row0 + lane;
+            float g = 0.0f;
+            if (r < rows) {
+                const float o = s_o[wave][lane], yy = y[r];
+                const float qq = 1.0f / (1.0f + expf(-o));
+                g = (qq - yy) * inv_rows;
+                // softplus(o) - y o
+                const float sp = o > 0.0f ? o + log1pf(expf(-o)) : log1pf(expf(o));
+                lsum += sp - yy * o;
+                db2 += g;
+            }
+            s_o[wave][lane] = g;
         }
-        for (int off = 1; off < 32; off <<= 1)
-            for (int i = 0; i < 16; ++i) s[i] += __shfl_xor(s[i], off, 64);
-        float o[16], g[16];
-        for (int i = 0; i < 16; ++i) {
-            const int64_t r = tile * 32 + (i / 4) * 8 + half * 4 + (i % 4);
-            o[i] = s[i] + b2;
-            const float qq = 1.0f / (1.0f + expf(-o[i]));
-            if (!kBackward) {
-                if (col_in == 0 && r < rows) q_out[r] = qq;
-            } else {
-                float yy = 0.0f;
-                if (r < rows) yy = y[r];
-                g[i] = r < rows ? (qq - yy) * inv_rows : 0.0f;
-                if (col_in == 0 && r < rows) {
-                    // softplus(o) - y o
-                    const float sp = o[i] > 0.0f ? o[i] + log1pf(expf(-o[i])) : log1pf(expf(o[i]));
-                    lsum += sp - yy * o[i];
-                    db2 += g[i];
+        __syncthreads();
+        // ---- pass 2: columns of chunks 2 wave, 2 wave + 1 over the 4 tiles ----
+        for (int t = 0; t < kWaves; ++t) {
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(&s_x[t][col_in * kF + half * 8]);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(&s_x[t][col_in * kF + 16 + half * 8]);
+            uint32_t t0[4], t1[4];   // x^T with rows in the D-register order
+            for (int m = 0; m < 8; m += 2) {
+                const int r0 = d_row(m, half), r1 = d_row(8 + m, half);
+                t0[m >> 1] = *reinterpret_cast<const uint32_t *>(&s_xt[t][col_in * 32 + r0]);
+                t1[m >> 1] = *reinterpret_cast<const uint32_t *>(&s_xt[t][col_in * 32 + r1]);
+            }
+            const bf16x8 ax0 = __builtin_bit_cast(bf16x8, make_uint4(t0[0], t0[1], t0[2], t0[3]));
+            const bf16x8 ax1 = __builtin_bit_cast(bf16x8, make_uint4(t1[0], t1[1], t1[2], t1[3]));
+            float g[16];
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const float4 v = *reinterpret_cast<const float4 *>(&s_o[t][q4 * 8 + half * 4]);
+                g[4 * q4] = v.x;
+                g[4 * q4 + 1] = v.y;
+                g[4 * q4 + 2] = v.z;
+                g[4 * q4 + 3] = v.w;
+            }
+            for (int c = 0; c < 2; ++c) {
+                const int j = 2 * wave + c, col = j * 32 + col_in;
+                const f32x16 acc = hidden_chunk(s_w1t, j, lane, a0, a1);
+                const float bb = s_b1[col], ww = s_w2[col];
+                uint32_t dq[8];
+                for (int i = 0; i < 16; ++i) {
+                    const float pre = acc[i] + bb;
+                    dw2[c] += g[i] * fmaxf(pre, 0.0f);
+                    const float dh = pre > 0.0f ? g[i] * ww : 0.0f;
+                    db1[c] += dh;
+                    const uint32_t bits = bf16_bits(dh);
+                    dq[i >> 1] = (i & 1) ? (dq[i >> 1] | (bits << 16)) : bits;
                 }
+                const bf16x8 d0 = __builtin_bit_cast(bf16x8, make_uint4(dq[0], dq[1], dq[2], dq[3]));
+                const bf16x8 d1 = __builtin_bit_cast(bf16x8, make_uint4(dq[4], dq[5], dq[6], dq[7]));
+                dw1[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax0, d0, dw1[c], 0, 0, 0);
+                dw1[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax1, d1, dw1[c], 0, 0, 0);
             }
         }
-        if (!kBackward) continue;
-        // ---- pass 2: hidden-layer gradients ----
-        __builtin_amdgcn_wave_barrier();
-        uint32_t t0[4], t1[4];   // x^T with rows in the D-register order
-        for (int m = 0; m < 8; m += 2) {
-            const int r0 = (m / 4) * 8 + half * 4 + (m % 4);          // step 0: i = m, m + 1
-            const int r1 = ((8 + m) / 4) * 8 + half * 4 + (m % 4);    // step 1: i = 8 + m, 9 + m
-            t0[m >> 1] = (uint32_t)s_xt[wave][col_in * 32 + r0] | ((uint32_t)s_xt[wave][col_in * 32 + r0 + 1] << 16);
-            t1[m >> 1] = (uint32_t)s_xt[wave][col_in * 32 + r1] | ((uint32_t)s_xt[wave][col_in * 32 + r1 + 1] << 16);
-        }
-        const bf16x8 ax0 = __builtin_bit_cast(bf16x8, make_uint4(t0[0], t0[1], t0[2], t0[3]));
-        const bf16x8 ax1 = __builtin_bit_cast(bf16x8, make_uint4(t1[0], t1[1], t1[2], t1[3]));
-        for (int j = 0; j < 8; ++j) {
-            const int col = j * 32 + col_in;
-            const bf16x8 bw0 = *reinterpret_cast<const bf16x8 *>(s_w1t + col * kF + half * 8);
-            const bf16x8 bw1 = *reinterpret_cast<const bf16x8 *>(s_w1t + col * kF + 16 + half * 8);
-            f32x16 acc = {};
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw1, acc, 0, 0, 0);
-            const float bb = s_b1[col], ww = s_w2[col];
-            uint32_t dq[8];
-            for (int i = 0; i < 16; ++i) {
-                const float pre = acc[i] + bb;
-                const float h = fmaxf(pre, 0.0f);
-                dw2[j] += g[i] * h;
-                const float dh = pre > 0.0f ? g[i] * ww : 0.0f;
-                db1[j] += dh;
-                const uint32_t bits = bf16_bits(dh);
-                dq[i >> 1] = (i & 1) ? (dq[i >> 1] | (bits << 16)) : bits;
-            }
-            const bf16x8 d0 = __builtin_bit_cast(bf16x8, make_uint4(dq[0], dq[1], dq[2], dq[3]));
-            const bf16x8 d1 = __builtin_bit_cast(bf16x8, make_uint4(dq[4], dq[5], dq[6], dq[7]));
-            dw1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax0, d0, dw1[j], 0, 0, 0);
-            dw1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax1, d1, dw1[j], 0, 0, 0);
-        }
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();                                // before the next step's tiles overwrite LDS
     }
-    if (!kBackward) return;
-    // ---- reduce this wave's gradient partials into the global buffer ----
-    for (int j = 0; j < 8; ++j) {
-        const int col = j * 32 + col_in;
-        for (int i = 0; i < 16; ++i) {
-            const int f = (i / 4) * 8 + half * 4 + (i % 4);
-            atomicAdd(&grad[kOffW1 + f * kH + col], dw1[j][i]);
-        }
-        const float w2s = dw2[j] + __shfl_xor(dw2[j], 32, 64);
-        const float b1s = db1[j] + __shfl_xor(db1[j], 32, 64);
+    // ---- the workgroup's row of the workspace (plain stores) ----
+    float *row = part + (size_t)blockIdx.x * (HP_MLP_PARAMS + 1);
+    for (int c = 0; c < 2; ++c) {
+        const int col = (2 * wave + c) * 32 + col_in;
+        for (int i = 0; i < 16; ++i) row[kOffW1 + d_row(i, half) * kH + col] = dw1[c][i];
+        // both halves of the wave hold partials of column col
+        const float w2s = dw2[c] + __shfl_xor(dw2[c], 32, 64);
+        const float b1s = db1[c] + __shfl_xor(db1[c], 32, 64);
         if (half == 0) {
-            atomicAdd(&grad[kOffW2 + col], w2s);
-            atomicAdd(&grad[kOffB1 + col], b1s);
+            row[kOffW2 + col] = w2s;
+            row[kOffB1 + col] = b1s;
         }
     }
-    if (col_in == 0) {
-        atomicAdd(&grad[kOffB2], db2);
-        atomicAdd(loss_sum, lsum);
+    // b2 and the loss: a fixed butterfly over the wave, then the waves in order
+    for (int off = 1; off < 64; off <<= 1) {
+        db2 += __shfl_xor(db2, off, 64);
+        lsum += __shfl_xor(lsum, off, 64);
+    }
+    if (lane == 0) {
+        s_red[wave][0] = db2;
+        s_red[wave][1] = lsum;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float b = s_red[0][0], l = s_red[0][1];
+        for (int w = 1; w < kWaves; ++w) {
+            b += s_red[w][0];
+            l += s_red[w][1];
+        }
+        row[kOffB2] = b;
+        row[HP_MLP_PARAMS] = l;
+    }
+}
+
+// grad[p] (p < HP_MLP_PARAMS) and the loss (p = HP_MLP_PARAMS) = the sum of
+// column p over the workspace's first `parts` rows, in a fixed order: 16 row
+// groups per column summed by 16 waves, then the groups in order.  A wave
+// reads 64 consecutive columns of a row (256 bytes) per load.
+__global__ __launch_bounds__(1024) void mlp_reduce_kernel(const float *__restrict__ part, int parts,
+                                                          float *__restrict__ grad, float *__restrict__ loss_sum) {
+    __shared__ float s[16][64];
+    const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + c;
+    const int per = (parts + 15) / 16, lo = grp * per, hi = min(parts, lo + per);
+    float sum = 0.0f;
+    if (p <= HP_MLP_PARAMS)
+        for (int b = lo; b < hi; ++b) sum += part[(size_t)b * (HP_MLP_PARAMS + 1) + p];
+    s[grp][c] = sum;
+    __syncthreads();
+    if (grp == 0 && p <= HP_MLP_PARAMS) {
+        float t = s[0][c];
+        for (int k = 1; k < 16; ++k) t += s[k][c];
+        if (p < HP_MLP_PARAMS) grad[p] = t;
+        else *loss_sum = t;
     }
 }
 
@@ -312,14 +429,14 @@ hipError_t launch_features(const Plan &p, float *acc, uint16_t *x, hipStream_t s
 
 hipError_t launch_mlp(const hp_mlp &net, const uint16_t *x, const float *y, int64_t rows, float *q, float *loss_sum,
                       bool backward, hipStream_t s) {
-    const int64_t tiles = (rows + 31) / 32;
-    const int grid = grid_for(tiles, kWaves, 1024);
     if (backward) {
-        zero_f32_kernel<<<grid_for(HP_MLP_PARAMS, 256, 64), 256, 0, s>>>(net.grad, HP_MLP_PARAMS);
-        zero_f32_kernel<<<1, 64, 0, s>>>(loss_sum, 1);
-        mlp_kernel<true><<<grid, kWaves * 64, 0, s>>>(x, y, rows, net.params, net.w_bf16, nullptr, net.grad, loss_sum);
+        // 128 rows per workgroup step; one workspace row per workgroup
+        const int grid = grid_for((rows + 127) / 128, 1, HP_MLP_PARTS);
+        mlp_backward_kernel<<<grid, kWaves * 64, 0, s>>>(x, y, rows, net.params, net.w_bf16, net.partials);
+        mlp_reduce_kernel<<<(HP_MLP_PARAMS + 1 + 63) / 64, 1024, 0, s>>>(net.partials, grid, net.grad, loss_sum);
     } else {
-        mlp_kernel<false><<<grid, kWaves * 64, 0, s>>>(x, nullptr, rows, net.params, net.w_bf16, q, nullptr, nullptr);
+        const int grid = grid_for((rows + 31) / 32, kWaves, 1024);
+        mlp_forward_kernel<<<grid, kWaves * 64, 0, s>>>(x, rows, net.params, net.w_bf16, q);
     }
     return hipGetLastError();
 }

@@ -31,12 +31,13 @@ from . import workload as wl
 
 F_IN, HIDDEN = 32, 256
 N_PARAMS = F_IN * HIDDEN + 2 * HIDDEN + 1
+MLP_PARTS = 1024                     # rows of the backward pass's partial-sum workspace
 WEIGHTS_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "learned_init_weights.json")
 
 
 class HpMlp(ct.Structure):
     _fields_ = [("params", ct.c_void_p), ("adam_m", ct.c_void_p), ("adam_v", ct.c_void_p),
-                ("grad", ct.c_void_p), ("w_bf16", ct.c_void_p)]
+                ("grad", ct.c_void_p), ("w_bf16", ct.c_void_p), ("partials", ct.c_void_p)]
 
 
 def _lib():
@@ -81,13 +82,14 @@ class MLP:
         self.v = torch.zeros(N_PARAMS, **f32)
         self.grad = torch.zeros(N_PARAMS, **f32)
         self.w_bf16 = torch.zeros(F_IN * HIDDEN + HIDDEN, dtype=torch.int16, device=device)
+        self.partials = torch.empty(MLP_PARTS * (N_PARAMS + 1), **f32)
         self.loss_buf = torch.zeros(1, **f32)
         self.step = 0
         self.sync()
 
     def c_struct(self):
         return HpMlp(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
-                     self.grad.data_ptr(), self.w_bf16.data_ptr())
+                     self.grad.data_ptr(), self.w_bf16.data_ptr(), self.partials.data_ptr())
 
     def sync(self):
         hp._check(_lib().hp_mlp_sync(ct.byref(self.c_struct()), _stream()))
@@ -280,7 +282,8 @@ def evaluate(net, n_formulas, n_vars=2048, seed=4, chains=64, sweeps=(20, 100, 5
 
 def mlp_bench(rows, rounds=5, seed=4):
     """Time the MLP kernels alone on `rows` random feature rows: forward, and
-    forward + backward (one fused kernel) + Adam, `rounds` times each after a
+    the training step (backward kernel with the forward recomputed, the
+    fixed-order reduction of its partial sums, Adam), `rounds` times each after a
     warm-up.  Algorithmic work per row: the forward product 2 * 32 * 256 and
     the output 2 * 256 flops; the backward recomputes the forward and adds
     dh = w2 * relu'(h) (256), dW1 = x^T dh (2 * 32 * 256) and dw2 (2 * 256).

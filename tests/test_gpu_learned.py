@@ -69,17 +69,23 @@ def test_forward_matches_oracle(hip, rows):
     assert np.max(np.abs(q.cpu().numpy() - want)) < 2e-6
 
 
-def test_backward_and_adam_match_oracle(hip):
+def _rows(rows, seed):
     import torch
-    net = _net(12)
-    rng = np.random.default_rng(7)
-    rows = 3000
+    rng = np.random.default_rng(seed)
     xf = M.bf16_round(rng.standard_normal((rows, M.F_IN)))
     y = rng.uniform(0, 1, rows)
     bits = torch.tensor((xf.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16),
                         device="cuda")
-    yt = torch.tensor(y.astype(np.float32), device="cuda")
-    say("[mlp backward] rows=3000")
+    return xf, y, bits, torch.tensor(y.astype(np.float32), device="cuda")
+
+
+# 3000 rows: 24 workgroups of one tile per wave; 300 000 rows: all 1024
+# workspace rows, each of the 4096 waves summing 2 or 3 tiles
+@pytest.mark.parametrize("rows", [3000, 300000])
+def test_backward_and_adam_match_oracle(hip, rows):
+    net = _net(12)
+    xf, y, bits, yt = _rows(rows, 7)
+    say(f"[mlp backward] rows={rows}")
     loss = net.backward(bits, yt)
     _sync()
     W1, b1, w2, b2 = _oracle_params(net)
@@ -104,6 +110,22 @@ def test_backward_and_adam_match_oracle(hip):
     wb = _bits_to_float(net.w_bf16)
     W1n = net.host_params()[:M.F_IN * M.HIDDEN].reshape(M.F_IN, M.HIDDEN)
     assert np.array_equal(wb[:M.F_IN * M.HIDDEN].reshape(M.HIDDEN, M.F_IN), M.bf16_round(W1n).T)
+
+
+def test_backward_is_deterministic(hip):
+    """The gradient and the loss are sums in a fixed order (per workgroup,
+    then over the workgroups' rows): the same input gives the same bits, also
+    after a larger call has filled more of the workspace."""
+    net = _net(13)
+    _, _, bits, yt = _rows(5000, 8)
+    _, _, big_bits, big_yt = _rows(200000, 9)
+    say("[mlp backward] determinism, rows=5000 / 200000 / 5000")
+    first = (net.backward(bits, yt).clone(), net.grad.clone())
+    net.backward(big_bits, big_yt)
+    again = (net.backward(bits, yt).clone(), net.grad.clone())
+    _sync()
+    assert np.array_equal(first[0].cpu().numpy(), again[0].cpu().numpy())
+    assert np.array_equal(first[1].cpu().numpy(), again[1].cpu().numpy())
 
 
 def test_init_chains_and_chain_mean_match_oracle(hip):
