@@ -138,6 +138,24 @@ def test_run_rejects_null_plan_and_state(lib):
     assert lib.hp_plan_query(None, None) == hp.HP_EINVAL
 
 
+def test_mlp_calls_reject_missing_buffers(lib):
+    """The learned initializer's calls check their buffers before launching:
+    a network without its backward workspace, or a null input, is refused
+    (the pointers are never dereferenced on these paths)."""
+    from paper_2311_02101_amd import learned as Lr
+    Lr._lib()                                        # argtypes
+    fake = ct.c_void_p(0x1000)
+    no_ws = Lr.HpMlp(fake, fake, fake, fake, fake, None)
+    assert lib.hp_mlp_backward(ct.byref(no_ws), fake, fake, 32, fake, None) == hp.HP_EINVAL
+    assert b"null" in lib.hp_last_error()
+    full = Lr.HpMlp(fake, fake, fake, fake, fake, fake)
+    assert lib.hp_mlp_backward(ct.byref(full), None, fake, 32, fake, None) == hp.HP_EINVAL
+    assert lib.hp_mlp_backward(ct.byref(full), fake, fake, 0, fake, None) == hp.HP_EINVAL
+    assert lib.hp_mlp_forward(ct.byref(full), fake, 0, fake, None) == hp.HP_EINVAL
+    assert lib.hp_mlp_adam(ct.byref(full), 1e-3, 0.9, 0.999, 1e-8, 0, None) == hp.HP_EINVAL
+    assert lib.hp_mlp_sync(None, None) == hp.HP_EINVAL
+
+
 def test_binding_refuses_missing_library(tmp_path, monkeypatch):
     monkeypatch.setattr(hp, "LIB_PATH", str(tmp_path / "libhp.so"))
     monkeypatch.setattr(hp, "_lib", None)
