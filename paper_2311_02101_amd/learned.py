@@ -14,6 +14,7 @@ buffers and drives the loop.
 
     python -m paper_2311_02101_amd.learned --instances 100000   # full-size training run
     python -m paper_2311_02101_amd.learned --mlp-bench 4194304  # MLP kernels alone (JSON)
+    python -m paper_2311_02101_amd.learned --equal-accuracy 256 # learned form vs plain at equal accuracy
 """
 from __future__ import annotations
 
@@ -280,6 +281,93 @@ def evaluate(net, n_formulas, n_vars=2048, seed=4, chains=64, sweeps=(20, 100, 5
     return out
 
 
+def _event_seconds(fn):
+    """HIP-event time of fn() on the current stream (synchronised)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def equal_accuracy(net, n_formulas, n_vars=2048, seed=4, chains=64, budget=20, step=5, max_sweeps=1000,
+                   first=10 ** 6, precisions=("f64", "f32")):
+    """Speed-up of the learned form over the plain method at equal accuracy.
+
+    Accuracy is the mean over the formulas of the best satisfied-clause
+    count of all B chains.  Learned form (FP32): chains [0, B/2) start from
+    Bernoulli(q), chains [B/2, B) uniform, `budget` sweeps.  Plain method, in
+    each of `precisions`: all B chains uniform (the same initial states,
+    temperatures and random streams as the learned run's uniform half), run
+    `step` sweeps at a time until its accuracy reaches the learned form's.
+    Times are HIP-event times of fresh runs: the learned form's includes the
+    features, the forward pass and the initial draws; the plain form's is one
+    run of the sweeps it needed.  Per formula, the sweeps the plain run needs
+    to reach that formula's learned count are reported too (max_sweeps + step
+    where it never does)."""
+    import torch
+    W, b, _ = wl.pretrained_rbm(7, wl.FSTAR_PAIR)
+    tables = _formulas(n_formulas, n_vars, seed, first)
+    ns = [n_vars] * n_formulas
+    half = chains // 2
+    temps = np.concatenate([wl.default_temperatures(half, 2)] * 2).astype(np.int32)
+    v0 = [wl.initial_state(chains, n_vars, seed, tag=first + f) for f in range(n_formulas)]
+
+    def best_of(plan, st):
+        plan.check()
+        return st.s_max.cpu().numpy().reshape(n_formulas, chains).max(axis=1)
+
+    lplan = hp.Plan(tables, ns, W, b, chains=chains, temps=temps, precision="f32", seed=seed + 7)
+
+    def learned_run(st):
+        q = net.forward(features(lplan))
+        init_chains(lplan, q, st, 0, half)
+        lplan.run(st, budget)
+        lplan.run(st, 0)
+
+    learned_run(lplan.new_state(v0))                       # warm-up (module load, first launches)
+    st = lplan.new_state(v0)
+    torch.cuda.synchronize()
+    t_learned = _event_seconds(lambda: learned_run(st))
+    target_f = best_of(lplan, st)
+    lplan.free()
+    target = float(target_f.mean())
+    out = {"formulas": n_formulas, "n_vars": n_vars, "chains": chains, "budget": budget, "step": step,
+           "learned": {"precision": "f32", "sweeps": budget, "accuracy": target, "seconds": t_learned}}
+    for prec in precisions:
+        plan = hp.Plan(tables, ns, W, b, chains=chains, temps=temps, precision=prec, seed=seed + 7)
+        st = plan.new_state(v0)
+        plan.run(st, 0)
+        need_f = np.full(n_formulas, max_sweeps + step)
+        need, acc, done = None, [], 0
+        while done < max_sweeps:
+            plan.run(st, step)
+            plan.run(st, 0)
+            done += step
+            best = best_of(plan, st)
+            acc.append((done, float(best.mean())))
+            need_f[(need_f > max_sweeps) & (best >= target_f)] = done
+            if need is None and best.mean() >= target:
+                need = done
+            if need is not None and (need_f <= max_sweeps).all():
+                break
+        res = {"precision": prec, "sweeps_to_equal_accuracy": need, "accuracy_by_sweeps": acc,
+               "per_formula_sweeps_median": float(np.median(need_f)),
+               "per_formula_reached": int((need_f <= max_sweeps).sum())}
+        if need is not None:
+            plan.run(plan.new_state(v0), need)             # warm-up of the same launch
+            st = plan.new_state(v0)
+            torch.cuda.synchronize()
+            res["seconds"] = _event_seconds(lambda: (plan.run(st, need), plan.run(st, 0)))
+            res["accuracy"] = float(best_of(plan, st).mean())
+            res["speedup_of_learned_form"] = res["seconds"] / t_learned
+        plan.free()
+        out["plain_" + prec] = res
+    return out
+
+
 def mlp_bench(rows, rounds=5, seed=4):
     """Time the MLP kernels alone on `rows` random feature rows: forward, and
     the training step (backward kernel with the forward recomputed, the
@@ -330,9 +418,19 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--out", default=WEIGHTS_JSON)
     ap.add_argument("--workers", type=int, default=16, help="host processes generating formulas")
+    ap.add_argument("--equal-accuracy", type=int, default=0,
+                    help="only compare the committed network's learned form with the plain method at equal "
+                         "accuracy on this many held-out formulas and print JSON")
+    ap.add_argument("--budget", type=int, default=20, help="sweeps of the learned form (--equal-accuracy)")
+    ap.add_argument("--step", type=int, default=1, help="sweeps between the plain runs' counts (--equal-accuracy)")
     args = ap.parse_args(argv)
     if args.mlp_bench > 0:
         print(json.dumps(mlp_bench(args.mlp_bench)), flush=True)
+        return 0
+    if args.equal_accuracy > 0:
+        net, _ = MLP.load()
+        print(json.dumps(equal_accuracy(net, args.equal_accuracy, args.n_vars, args.seed,
+                                        budget=args.budget, step=args.step)), flush=True)
         return 0
     pool = FormulaPool(args.workers)      # forked before the GPU is used
 
