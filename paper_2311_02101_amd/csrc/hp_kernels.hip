@@ -671,6 +671,14 @@ __device__ __forceinline__ RecView rec_view(const uint4 *rec, const uint32_t *or
                    __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(orig), (short)0, M * 4, kRawBufferWord3)};
 }
 
+// Keeps every word of a loaded record, and its first Philox block, in
+// registers of its own until the record's clause runs.  A word the clause
+// length leaves unused would otherwise be given to a temporary of the clause
+// before it, and writing that temporary waits for the prefetch to land.
+__device__ __forceinline__ void rec_hold(const uint4 &r, uint32_t oc) {
+    asm volatile("" ::"v"(r.x), "v"(r.y), "v"(r.z), "v"(r.w), "v"(oc));
+}
+
 __device__ __forceinline__ void rec_load(const RecView &rv, int first, int lane, uint4 &r, uint32_t &oc) {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(rv.rec, lane * 16, first * 16, 0);
     r = make_uint4(v[0], v[1], v[2], v[3]);
@@ -721,7 +729,10 @@ __device__ __forceinline__ int take_step(const StepCounter &sc, int lane, int pr
 // is the wave's current step number: if it is in this run, the wave
 // processes it and keeps taking steps until it gets one past the run, which
 // it leaves in `k` for the next run.  The next step's records are loaded
-// while the current ones are processed (two register sets, no copies).
+// while the current ones are processed (two register sets, no copies).  The
+// load is issued on every iteration, past the run's end from the current
+// step again (its values are never used), so the wait for a step's records
+// counts the one load issued after them on every path.
 template <int LEN, bool kSample, bool kClust, int NB, int kTab>
 __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &rv, int lo, int hi, int olo, int ohi,
                                               int &k, const StepCounter &sc, int lane, const PhiloxSweep &ps,
@@ -735,14 +746,16 @@ __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &r
     for (;;) {
         int kn = take_step(sc, lane, k);
         int next = lo + (kn - olo) * kWave;
-        if (kn < ohi) rec_load(rv, next, lane, rb, ob);
+        rec_load(rv, kn < ohi ? next : base, lane, rb, ob);
+        rec_hold(ra, oa);
         if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB, kTab>(L, ra, oa, ps, key, nbh, full, lmask);
         k = kn;
         if (kn >= ohi) break;
         base = next;
         kn = take_step(sc, lane, k);
         next = lo + (kn - olo) * kWave;
-        if (kn < ohi) rec_load(rv, next, lane, ra, oa);
+        rec_load(rv, kn < ohi ? next : base, lane, ra, oa);
+        rec_hold(rb, ob);
         if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB, kTab>(L, rb, ob, ps, key, nbh, full, lmask);
         k = kn;
         if (kn >= ohi) break;
