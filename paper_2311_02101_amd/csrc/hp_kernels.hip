@@ -279,8 +279,7 @@ __device__ __forceinline__ uint32_t hidden_mask(const uint32_t *row, uint32_t bl
         // both blocks in one pass (interleaved rounds, one key schedule)
         const uint4 tb = *reinterpret_cast<const uint4 *>(row + 4);
         uint4 r[2];
-        const uint32_t w[2] = {kPhaseHidden | blk, kPhaseHidden | (blk + 1u)};
-        philox_sweep_multi<2>(r, w, u, key);
+        philox_sweep_pair(r, kPhaseHidden | blk, u, key);     // blocks blk, blk + 1 (blk even, < 2^31)
         uint32_t m = draw_first(r[1].w, tb.w);
         m = draw_next(m, r[1].z, tb.z);
         m = draw_next(m, r[1].y, tb.y);
@@ -622,18 +621,27 @@ __device__ __forceinline__ void table_reads(const PushLds &L, uint32_t n, int64_
     }
 }
 
+// cnt += (m != 0) as one compare and one add-with-carry, issued where m is
+// made; in the plain C form the compiler recomputes m from its parts at the
+// end of the clause (three instructions)
+__device__ __forceinline__ void count_satisfied(int &cnt, uint32_t m) {
+    asm volatile("v_cmp_ne_u32 vcc, 0, %1\n\tv_addc_co_u32 %0, vcc, 0, %0, vcc" : "+v"(cnt) : "v"(m) : "vcc");
+}
+
 // One clause of compile-time length LEN: gather, literal-truth pattern,
 // count; when sampling, the hidden draw and the scatter of its
-// contributions into the LDS accumulators.  Returns 1 if it is satisfied.
+// contributions into the LDS accumulators.  Adds 1 to cnt if it is
+// satisfied.
 // kClust: the size-clustered model; a clause of length len takes the tables
 // of group K = max(len, 3) (L = 3 or K + 1 hidden units, drawn from blocks
 // 2c and, for L > 4, 2c + 1), and nbh, full and lmask are unused.
 template <int LEN, bool kSample, bool kClust, int NB, int kTab>
-__device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint32_t oc, const PhiloxSweep &ps,
-                                          Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask) {
+__device__ __forceinline__ void clause_one(const PushLds &L, const uint4 &r, uint32_t oc, const PhiloxSweep &ps,
+                                           Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask, int &cnt) {
     // size-clustered model: the padded pattern; padded model: the pattern of
     // the LEN literals alone (its threshold row holds the padded one's)
     const uint32_t m = kClust ? pattern_fixed<LEN, kClust>(L.v, r, full) : gather_fixed<LEN>(L.v, r) ^ (r.w >> 19);
+    count_satisfied(cnt, m);
     if (kSample) {
         int64_t g[8];
         if (kClust) {
@@ -653,7 +661,6 @@ __device__ __forceinline__ int clause_one(const PushLds &L, const uint4 &r, uint
         }
         scatter_slots<0, LEN>(L.x, r, g);
     }
-    return m != 0u ? 1 : 0;
 }
 
 // A wave's view of a range of clause records: raw buffer descriptors over
@@ -706,23 +713,36 @@ struct StepCounter {
     int wave, nw;
 };
 
-// One LDS add-and-return of 1 by the calling lane.  The compiler's atomic
-// form wraps an add at a uniform address in a whole-wave reduction (lane
-// counts, prefix, two broadcasts: 8 VALU instructions per step, i.e. per
-// clause); here only the add and the wait for its result, which sits in the
-// same asm block so the returned register is never read early.
-__device__ __forceinline__ int lds_fetch_add1(int *p) {
-    const uint32_t a = (uint32_t)(size_t)(__attribute__((address_space(3))) int *)p;
+// One LDS add-and-return of 1 for the wave, by lane 0 alone, its result
+// returned to every lane in a scalar register.  The compiler's atomic form
+// wraps an add at a uniform address in a whole-wave reduction (lane counts,
+// prefix, two broadcasts: 8 VALU instructions per step, i.e. per clause), and
+// a branch on lane 0 costs a zeroed result register, the address moved into a
+// vector register and the exec-mask save and restore around it.  Here one
+// asm block narrows exec to lane 0, issues the add, waits for its result
+// (so the returned register is never read early), restores exec and reads
+// lane 0.  The whole wave must be active (lane 0 in exec).
+__device__ __forceinline__ int lds_fetch_add1_wave(uint32_t a, uint32_t one) {
     int k;
-    asm volatile("ds_add_rtn_u32 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=v"(k) : "v"(a), "v"(1) : "memory");
+    uint64_t saved;
+    uint32_t r;
+    asm volatile(
+        "s_mov_b64 %1, exec\n\t"
+        "s_mov_b64 exec, 1\n\t"
+        "ds_add_rtn_u32 %2, %3, %4\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 exec, %1\n\t"
+        "v_readfirstlane_b32 %0, %2"
+        : "=s"(k), "=&s"(saved), "=&v"(r)
+        : "v"(a), "v"(one)
+        : "memory");
     return k;
 }
 
-__device__ __forceinline__ int take_step(const StepCounter &sc, int lane, int prev) {
+__device__ __forceinline__ int take_step(const StepCounter &sc, int prev) {
     if (!sc.dyn) return prev < 0 ? sc.wave : prev + sc.nw;
-    int k = 0;
-    if (lane == 0) k = lds_fetch_add1(sc.ctr);
-    return __builtin_amdgcn_readfirstlane(k) - sc.base;
+    const uint32_t a = (uint32_t)(size_t)(__attribute__((address_space(3))) int *)sc.ctr;
+    return lds_fetch_add1_wave(a, 1u) - sc.base;
 }
 
 // The steps [olo, ohi) of the run [lo, hi) of clauses of length LEN.  `k`
@@ -744,19 +764,19 @@ __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &r
     uint32_t oa, ob;
     rec_load(rv, base, lane, ra, oa);
     for (;;) {
-        int kn = take_step(sc, lane, k);
+        int kn = take_step(sc, k);
         int next = lo + (kn - olo) * kWave;
         rec_load(rv, kn < ohi ? next : base, lane, rb, ob);
         rec_hold(ra, oa);
-        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB, kTab>(L, ra, oa, ps, key, nbh, full, lmask);
+        if (lane < hi - base) clause_one<LEN, kSample, kClust, NB, kTab>(L, ra, oa, ps, key, nbh, full, lmask, cnt);
         k = kn;
         if (kn >= ohi) break;
         base = next;
-        kn = take_step(sc, lane, k);
+        kn = take_step(sc, k);
         next = lo + (kn - olo) * kWave;
         rec_load(rv, kn < ohi ? next : base, lane, ra, oa);
         rec_hold(rb, ob);
-        if (lane < hi - base) cnt += clause_one<LEN, kSample, kClust, NB, kTab>(L, rb, ob, ps, key, nbh, full, lmask);
+        if (lane < hi - base) clause_one<LEN, kSample, kClust, NB, kTab>(L, rb, ob, ps, key, nbh, full, lmask, cnt);
         k = kn;
         if (kn >= ohi) break;
         base = next;
@@ -784,7 +804,7 @@ __device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &
     int32_t o[8];
     run_steps(bnd, o);
     int cnt = 0;
-    int k = take_step(sc, lane, -1);
+    int k = take_step(sc, -1);
 #define HP_SEG(LEN)                                                                                              \
     cnt += clause_segment<LEN, kSample, kClust, NB, kTab>(L, rv, bnd[LEN - 1], bnd[LEN], o[LEN - 1], o[LEN], k,  \
                                                           sc, lane, ps, key, nbh, full, lmask)

@@ -86,15 +86,15 @@ __device__ __forceinline__ PhiloxSweep philox_sweep_consts(uint32_t tlo, uint32_
 // first two rounds from the sweep constants (5 lane instructions instead of
 // 8), round 3 with a two-input XOR for word 0, then seven full rounds, the
 // NS chains interleaved round by round.
+// (philox_sweep_from takes round 1's products M1 w[i] already made.)
 template <int NS>
-__device__ __forceinline__ void philox_sweep_multi(uint4 (&x)[NS], const uint32_t (&w)[NS], const PhiloxSweep &u,
-                                                   Key2 key) {
+__device__ __forceinline__ void philox_sweep_from(uint4 (&x)[NS], const uint64_t (&p1)[NS], const PhiloxSweep &u,
+                                                  Key2 key) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)w[i];
-        const uint32_t a = (uint32_t)(p1 >> 32) ^ u.c1;            // word 0 after round 1
+        const uint32_t a = (uint32_t)(p1[i] >> 32) ^ u.c1;         // word 0 after round 1
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)a;
-        x[i] = make_uint4(u.a2 ^ (uint32_t)p1, 0u, (uint32_t)(p0 >> 32) ^ u.d2, (uint32_t)p0);
+        x[i] = make_uint4(u.a2 ^ (uint32_t)p1[i], 0u, (uint32_t)(p0 >> 32) ^ u.d2, (uint32_t)p0);
     }
     uint32_t k0 = key.k0 + 2u * 0x9E3779B9u, k1 = key.k1 + 2u * 0xBB67AE85u;   // round 3's key
 #pragma unroll
@@ -117,6 +117,29 @@ __device__ __forceinline__ void philox_sweep_multi(uint4 (&x)[NS], const uint32_
                               __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x[i].w, k1, 0x96), (uint32_t)p0);
         }
     }
+}
+
+template <int NS>
+__device__ __forceinline__ void philox_sweep_multi(uint4 (&x)[NS], const uint32_t (&w)[NS], const PhiloxSweep &u,
+                                                   Key2 key) {
+    uint64_t p1[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) p1[i] = (uint64_t)0xCD9E8D57u * (uint64_t)w[i];
+    philox_sweep_from<NS>(x, p1, u, key);
+}
+
+// The blocks w and w + 1 (w + 1 < 2^32, so M1 (w + 1) = M1 w + M1 without a
+// carry out of 64 bits): the second product is one multiply-add from w
+// instead of an add and a multiply.  Written as asm with M1 in a vector
+// register and the addend in a scalar pair (one scalar operand per
+// instruction), which the compiler's own form would move into vector
+// registers on every call.
+__device__ __forceinline__ void philox_sweep_pair(uint4 (&x)[2], uint32_t w, const PhiloxSweep &u, Key2 key) {
+    const uint32_t m1 = 0xCD9E8D57u;
+    uint64_t q;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(q) : "v"(w), "v"(m1), "s"((uint64_t)m1) : "vcc");
+    const uint64_t p1[2] = {(uint64_t)m1 * (uint64_t)w, q};
+    philox_sweep_from<2>(x, p1, u, key);
 }
 
 __device__ __forceinline__ uint4 philox_sweep(uint32_t w, const PhiloxSweep &u, Key2 key) {
