@@ -376,7 +376,16 @@ hp_status hp_plan(hp_plan_t *out, const hp_cnf *cnf, const hp_rbm *rbm, const hp
             uint32_t negm = 0;
             for (int k = 0; k < K; ++k) sl[k] = lits[(size_t)k * NC + c];
             for (int k = 0; k < len; ++k) negm |= (uint32_t)(sl[k] >> 15) << k;
-            sl[7] = (uint16_t)(len | (negm << 3));
+            // below seven literals the last word is the negation bits | 2^len
+            // alone (its XOR with the literals' values is the push kernels'
+            // threshold row 2^len + pattern); seven literals keep slot 6 and
+            // len | negm << 3 above it
+            if (len < 7) {
+                sl[6] = (uint16_t)(negm | (1u << len));
+                sl[7] = 0;
+            } else {
+                sl[7] = (uint16_t)(len | (negm << 3));
+            }
             rec[c0 + j] = make_uint4(sl[0] | ((uint32_t)sl[1] << 16), sl[2] | ((uint32_t)sl[3] << 16),
                                      sl[4] | ((uint32_t)sl[5] << 16), sl[6] | ((uint32_t)sl[7] << 16));
             orig[c0 + j] = (uint32_t)(c - c0) * blocks_per_clause;

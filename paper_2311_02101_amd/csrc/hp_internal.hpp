@@ -13,7 +13,7 @@ namespace hp {
 constexpr int kMaxK = 7;          // clause width limit (Sec. 3.1 assumes K <= 7)
 constexpr int kMaxL = 8;          // hidden units per clause: K+1 <= 8
 constexpr int kPatterns = 128;    // literal-truth patterns over K <= 7 inputs
-constexpr int kThrRows = 2 * kPatterns;   // push kernels: rows 2^len - 2 + (pattern of the len literals)
+constexpr int kThrRows = 2 * kPatterns;   // push kernels: rows 2^len + (pattern of the len literals)
 constexpr int kRowWords = 16;     // contribution table row: 8 slot words, 8 merged-padding words
 constexpr int kHidMasks = 256;    // hidden-state masks over L <= 8 units
 constexpr int kMaxVars = 32768;   // variable index packed in 15 bits
@@ -88,6 +88,14 @@ constexpr int kClustGfxRows = 488;
 constexpr int kClustGpad = 504;
 __host__ __device__ constexpr int clust_hidden(int K) { return K == 3 ? 3 : K + 1; }
 
+// clause length and negation bits from a record's last word (layout below)
+__device__ __forceinline__ uint32_t rec_len(uint32_t w) {
+    return (w >> 16) != 0u ? 7u : 31u - (uint32_t)__clz((int)w);
+}
+__device__ __forceinline__ uint32_t rec_negm(uint32_t w) {
+    return (w >> 16) != 0u ? (w >> 19) : (w ^ (1u << rec_len(w)));
+}
+
 // device pointers of the size RBMs (nullptr for a group no clause uses)
 struct ClustRbm {
     const double *W[kClustGroups];   // [T][K][L] of K = 3 + i
@@ -95,9 +103,12 @@ struct ClustRbm {
 };
 
 // Clause record of the push kernel: 8 x 16-bit slots in a uint4.  Slots
-// 0..6 hold literal k as (0-based variable index) | (negated << 15); slot 7
-// holds len | (negation bits of slots 0..len-1) << 3, where len is the
-// clause length (positions >= len repeat literal 0).  Records of a formula
+// 0..len-1 hold literal k as (0-based variable index) | (negated << 15),
+// where len is the clause length (positions >= len repeat literal 0).  The
+// last word holds, for len = 7, slot 6 and then len | (negation bits) << 3
+// in the high half; below seven literals it is the negation bits | 2^len
+// alone, so its XOR with the literals' values is the push kernels'
+// threshold row 2^len + pattern.  Records of a formula
 // are sorted by len (stable); orig[] keeps the first Philox block of the
 // clause's hidden draw, its index in the input times the blocks per clause,
 // which addresses its random numbers.

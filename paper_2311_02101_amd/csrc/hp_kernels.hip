@@ -527,11 +527,12 @@ __device__ __forceinline__ PushLds push_lds_clust(unsigned char *lds, int x_off)
                    reinterpret_cast<int64_t *>(lds + x_off), lds_at(kClustVOff), no_rows()};
 }
 
-// row of the padded pattern for row r = 2^len - 2 + m of the push kernels'
-// per-length threshold table (full = 2^K - 1; rows with len > K are unused)
+// row of the padded pattern for row r = 2^len + m of the push kernels'
+// per-length threshold table (full = 2^K - 1; rows 0, 1 and rows with
+// len > K are unused)
 __device__ __forceinline__ uint32_t padded_row(uint32_t r, uint32_t full) {
-    const uint32_t len = 31u - (uint32_t)__clz((int)(r + 2u));
-    const uint32_t m = r + 2u - (1u << len);
+    const uint32_t len = 31u - (uint32_t)__clz((int)r);
+    const uint32_t m = r - (1u << len);
     return (m | ((m & 1u) ? ~((1u << len) - 1u) : 0u)) & full;
 }
 
@@ -544,7 +545,7 @@ __device__ __forceinline__ void load_push_tables(const PushLds &L, const uint32_
         for (int i = tid; i < kClustGpad; i += NT) L.gpad[i] = gpad[tau * kClustGpad + i];
         return;
     }
-    for (int i = tid; i < (kThrRows - 2) * kMaxL; i += NT)
+    for (int i = 2 * kMaxL + tid; i < kThrRows * kMaxL; i += NT)
         L.thr[i] = thr[(tau * kPatterns + (int)padded_row((uint32_t)(i / kMaxL), full)) * kMaxL + i % kMaxL];
     const int64_t *rows = gfx + (size_t)tau * kHidMasks * kRowWords;
     if (kTab == kBucketPush) {
@@ -574,11 +575,16 @@ __device__ __forceinline__ uint32_t pad_mask(uint32_t len, uint32_t full) {
     return top & ~((1u << len) - 1u);
 }
 
-// literal-truth pattern of a clause of LEN literals (negation bits of slots
-// 0..LEN-1 in bits 19.. of the record's last word), padding filled
+// negation bits of a record of LEN literals (the record's last word)
+template <int LEN>
+__device__ __forceinline__ uint32_t neg_bits(const uint4 &r) {
+    return LEN < 7 ? r.w & ((1u << LEN) - 1u) : r.w >> 19;
+}
+
+// literal-truth pattern of a clause of LEN literals, padding filled
 template <int LEN, bool kClust>
 __device__ __forceinline__ uint32_t pattern_fixed(const uint8_t *v, const uint4 &r, uint32_t full) {
-    const uint32_t m = gather_fixed<LEN>(v, r) ^ (r.w >> 19);
+    const uint32_t m = gather_fixed<LEN>(v, r) ^ neg_bits<LEN>(r);
     return m | (pad_mask<kClust>((uint32_t)LEN, full) & (0u - (m & 1u)));
 }
 
@@ -621,11 +627,13 @@ __device__ __forceinline__ void table_reads(const PushLds &L, uint32_t n, int64_
     }
 }
 
-// cnt += (m != 0) as one compare and one add-with-carry, issued where m is
+// cnt += (m != Z) as one compare and one add-with-carry, issued where m is
 // made; in the plain C form the compiler recomputes m from its parts at the
-// end of the clause (three instructions)
+// end of the clause (three instructions).  Z <= 64 (an inline constant).
+template <uint32_t Z>
 __device__ __forceinline__ void count_satisfied(int &cnt, uint32_t m) {
-    asm volatile("v_cmp_ne_u32 vcc, 0, %1\n\tv_addc_co_u32 %0, vcc, 0, %0, vcc" : "+v"(cnt) : "v"(m) : "vcc");
+    static_assert(Z <= 64u, "the compare takes an inline constant");
+    asm volatile("v_cmp_ne_u32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, 0, %0, vcc" : "+v"(cnt) : "v"(m), "i"(Z) : "vcc");
 }
 
 // One clause of compile-time length LEN: gather, literal-truth pattern,
@@ -638,10 +646,16 @@ __device__ __forceinline__ void count_satisfied(int &cnt, uint32_t m) {
 template <int LEN, bool kSample, bool kClust, int NB, int kTab>
 __device__ __forceinline__ void clause_one(const PushLds &L, const uint4 &r, uint32_t oc, const PhiloxSweep &ps,
                                            Key2 key, uint32_t nbh, uint32_t full, uint32_t lmask, int &cnt) {
-    // size-clustered model: the padded pattern; padded model: the pattern of
-    // the LEN literals alone (its threshold row holds the padded one's)
-    const uint32_t m = kClust ? pattern_fixed<LEN, kClust>(L.v, r, full) : gather_fixed<LEN>(L.v, r) ^ (r.w >> 19);
-    count_satisfied(cnt, m);
+    // size-clustered model: the padded pattern.  Padded model: the pattern of
+    // the LEN literals alone, whose threshold row 2^LEN + m holds the padded
+    // pattern's; for LEN < 7 the record's last word is the negation bits |
+    // 2^LEN, so one XOR makes the row itself (a clause is satisfied iff its
+    // row is not 2^LEN).
+    constexpr bool kRow = !kClust && LEN < 7;
+    const uint32_t m = kClust  ? pattern_fixed<LEN, kClust>(L.v, r, full)
+                       : kRow ? gather_fixed<LEN>(L.v, r) ^ r.w
+                              : gather_fixed<LEN>(L.v, r) ^ neg_bits<LEN>(r);
+    count_satisfied<kRow ? (1u << LEN) : 0u>(cnt, m);
     if (kSample) {
         int64_t g[8];
         if (kClust) {
@@ -656,7 +670,7 @@ __device__ __forceinline__ void clause_one(const PushLds &L, const uint4 &r, uin
         } else {
             // units at and above L (drawn, not masked) index rows that
             // repeat row n mod 2^L
-            const uint32_t n = hidden_mask<NB>(L.thr + ((1u << LEN) - 2u + m) * kMaxL, oc, ps, key, 0u);
+            const uint32_t n = hidden_mask<NB>(L.thr + (kRow ? m : (1u << LEN) + m) * kMaxL, oc, ps, key, 0u);
             table_reads<LEN, kTab>(L, n, g);
         }
         scatter_slots<0, LEN>(L.x, r, g);
@@ -899,8 +913,8 @@ __device__ __forceinline__ int clause_phase_mfma(const PushLds &L, const uint4 *
             r = rec[c];
             oc = orig[c];
         }
-        const uint32_t len = (r.w >> 16) & 7u;
-        const uint32_t negm = r.w >> 19;
+        const uint32_t len = act ? rec_len(r.w) : 0u;
+        const uint32_t negm = act ? rec_negm(r.w) : 0u;
         const uint32_t e[7] = {r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16,
                                r.z & 0xffffu, r.z >> 16, r.w & 0xffffu};
         uint32_t m = 0;
@@ -935,7 +949,7 @@ __device__ __forceinline__ int clause_phase_mfma(const PushLds &L, const uint4 *
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if ((amb >> q) & 1u) {
-                    const uint32_t row = (1u << len) - 2u + (m & ((1u << len) - 1u));
+                    const uint32_t row = (1u << len) + (m & ((1u << len) - 1u));
                     const uint32_t bit = w4[q] <= L.thr[row * kMaxL + 4 * half + q] ? 1u : 0u;
                     nh = (nh & ~(1u << q)) | (bit << q);
                 }

@@ -57,7 +57,7 @@ __global__ void feature_count_kernel(const uint4 *__restrict__ rec, const int64_
         const uint4 r = rec[c];
         const uint32_t e[7] = {r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16, r.z & 0xffffu, r.z >> 16,
                                r.w & 0xffffu};
-        const int len = (int)((r.w >> 16) & 7u);
+        const int len = (int)rec_len(r.w);
         const float jw = ldexpf(1.0f, -len);
         for (int k = 0; k < len; ++k) {
             const int64_t v = v0 + (e[k] & 0x7fffu);

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kFeThreads) void free_energy_kernel(const FormulaDe
     for (int t = 0; t < kMaxTemperTemps; ++t) acc[t] = 0.0;
     for (int c = threadIdx.x; c < f.c; c += blockDim.x) {
         const uint4 q = r[c];
-        const uint32_t len = (q.w >> 16) & 7u, negm = q.w >> 19;
+        const uint32_t len = rec_len(q.w), negm = rec_negm(q.w);
         const uint32_t e[7] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16,
                                q.z & 0xffffu, q.z >> 16, q.w & 0xffffu};
         uint32_t m = 0;
