@@ -1012,19 +1012,23 @@ __device__ __forceinline__ uint8_t visible_update(int64_t xi, double fx_scale, R
     return (Real(word >> 8) * Real(1.0 / 16777216.0)) < rho ? 1 : 0;
 }
 
-// The FP32 form: the logit from the two 32-bit halves of the fixed-point
-// sum (single-rate conversions; |x| error about 2^-24 |x|), the logistic
-// function from the hardware exp2 and reciprocal (about 2^-24 |x| + 2 ulp
-// relative in exp(-x), so |d rho| <= 0.25 of that: below 4e-7 for
-// |x| <= 20), the moving average and the draw in FP32.
+// The FP32 form: -x log2(e) from the two 32-bit halves of the fixed-point
+// sum (single-rate conversions with the scale and -log2(e) folded into the
+// two constants; about 2^-23 |x| error), the logistic function from the
+// hardware exp2 and reciprocal (about 2 ulp more relative in exp(-x), so
+// |d rho| <= 0.25 of that: below 4e-7 for |x| <= 20), the moving average
+// and the draw in FP32.  The reciprocal is taken of (1 + e^-x) 2^-24, which
+// gives 2^24 rho with the same rounding as rho itself (a power-of-two
+// scale), so the draw compares the 24-bit uniform integer with it directly
+// and the average uses alpha 2^-48 (2^24 rho)(2^24 - 2^24 rho).
 template <>
 __device__ __forceinline__ uint8_t visible_update<float>(int64_t xi, double fx_scale, float &nu, float alpha,
                                                          uint32_t word) {
-    const float sc = (float)fx_scale;                          // 2^-S, exact
-    const float x = fmaf((float)(int32_t)(xi >> 32), sc * 4294967296.0f, (float)(uint32_t)xi * sc);
-    const float rho = __builtin_amdgcn_rcpf(1.0f + __expf(-x));
-    nu = ema(nu, rho, alpha);
-    return ((float)(word >> 8) * (1.0f / 16777216.0f)) < rho ? 1 : 0;
+    const float sc = (float)(fx_scale * -1.4426950408889634);  // -log2(e) 2^-S
+    const float y = fmaf((float)(int32_t)(xi >> 32), sc * 4294967296.0f, (float)(uint32_t)xi * sc);
+    const float rho24 = __builtin_amdgcn_rcpf(fmaf(__builtin_amdgcn_exp2f(y), 0x1p-24f, 0x1p-24f));
+    nu = fmaf(alpha * 0x1p-48f * rho24, 16777216.0f - rho24, (1.0f - alpha) * nu);
+    return (float)(word >> 8) < rho24 ? 1 : 0;
 }
 
 // workgroup total of a per-thread count (uses L.cnt; ends with a barrier)
