@@ -721,11 +721,19 @@ __device__ __forceinline__ void rec_load(const RecView &rv, int first, int lane,
 // k mod W, no counter): better when another workgroup shares the CU and
 // fills the SIMDs while this one waits at its barrier.
 struct StepCounter {
-    int *ctr;                    // LDS word, zeroed before the item's first sweep
     int base;                    // first number of this sweep
     int dyn;                     // 1: take steps from the counter; 0: round-robin
     int wave, nw;
 };
+
+// LDS byte address of the step counter (word 62 of the layout's counts,
+// zeroed before an item's first sweep); the sweep kernels have no static
+// LDS, so their dynamic LDS starts at address 0
+template <int kTab, bool kClust>
+constexpr int step_counter_addr() {
+    return (kClust ? kClustCntOff
+                   : kTab == kBucketWide ? kWideCntOff : kTab == kBucketMid ? kMidCntOff : kPushCntOff) + 62 * 4;
+}
 
 // One LDS add-and-return of 1 for the wave, by lane 0 alone, its result
 // returned to every lane in a scalar register.  The compiler's atomic form
@@ -735,28 +743,32 @@ struct StepCounter {
 // vector register and the exec-mask save and restore around it.  Here one
 // asm block narrows exec to lane 0, issues the add, waits for its result
 // (so the returned register is never read early), restores exec and reads
-// lane 0.  The whole wave must be active (lane 0 in exec).
-__device__ __forceinline__ int lds_fetch_add1_wave(uint32_t a, uint32_t one) {
+// lane 0.  The address is the register holding the added 1 plus the
+// instruction's offset (kAddr - 1), so no register is set up per step.  The
+// whole wave must be active (lane 0 in exec).
+template <int kAddr>
+__device__ __forceinline__ int lds_fetch_add1_wave(uint32_t one) {
+    static_assert(kAddr >= 1 && kAddr <= 65536, "the offset field holds 16 bits");
     int k;
     uint64_t saved;
     uint32_t r;
     asm volatile(
         "s_mov_b64 %1, exec\n\t"
         "s_mov_b64 exec, 1\n\t"
-        "ds_add_rtn_u32 %2, %3, %4\n\t"
+        "ds_add_rtn_u32 %2, %3, %3 offset:%4\n\t"
         "s_waitcnt lgkmcnt(0)\n\t"
         "s_mov_b64 exec, %1\n\t"
         "v_readfirstlane_b32 %0, %2"
         : "=s"(k), "=&s"(saved), "=&v"(r)
-        : "v"(a), "v"(one)
+        : "v"(one), "i"(kAddr - 1)
         : "memory");
     return k;
 }
 
+template <int kAddr>
 __device__ __forceinline__ int take_step(const StepCounter &sc, int prev) {
     if (!sc.dyn) return prev < 0 ? sc.wave : prev + sc.nw;
-    const uint32_t a = (uint32_t)(size_t)(__attribute__((address_space(3))) int *)sc.ctr;
-    return lds_fetch_add1_wave(a, 1u) - sc.base;
+    return lds_fetch_add1_wave<kAddr>(1u) - sc.base;
 }
 
 // The steps [olo, ohi) of the run [lo, hi) of clauses of length LEN.  `k`
@@ -778,7 +790,7 @@ __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &r
     uint32_t oa, ob;
     rec_load(rv, base, lane, ra, oa);
     for (;;) {
-        int kn = take_step(sc, k);
+        int kn = take_step<step_counter_addr<kTab, kClust>()>(sc, k);
         int next = lo + (kn - olo) * kWave;
         rec_load(rv, kn < ohi ? next : base, lane, rb, ob);
         rec_hold(ra, oa);
@@ -786,7 +798,7 @@ __device__ __forceinline__ int clause_segment(const PushLds &L, const RecView &r
         k = kn;
         if (kn >= ohi) break;
         base = next;
-        kn = take_step(sc, k);
+        kn = take_step<step_counter_addr<kTab, kClust>()>(sc, k);
         next = lo + (kn - olo) * kWave;
         rec_load(rv, kn < ohi ? next : base, lane, ra, oa);
         rec_hold(rb, ob);
@@ -818,7 +830,7 @@ __device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &
     int32_t o[8];
     run_steps(bnd, o);
     int cnt = 0;
-    int k = take_step(sc, -1);
+    int k = take_step<step_counter_addr<kTab, kClust>()>(sc, -1);
 #define HP_SEG(LEN)                                                                                              \
     cnt += clause_segment<LEN, kSample, kClust, NB, kTab>(L, rv, bnd[LEN - 1], bnd[LEN], o[LEN - 1], o[LEN], k,  \
                                                           sc, lane, ps, key, nbh, full, lmask)
@@ -1154,7 +1166,7 @@ __global__ __launch_bounds__(1024) void sweep_push_kernel(SweepParams<Real> P, W
                                                         full, lmask, P.K, a1, a2, 1.0 / fx_scale);
             else
             {
-                const StepCounter sc{L.cnt + 62, (int)s * steps, P.dyn_steps, wave_id, NT / kWave};
+                const StepCounter sc{(int)s * steps, P.dyn_steps, wave_id, NT / kWave};
                 cnt = sample ? clause_phase<true, kClust, kTab>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask)
                              : clause_phase<false, kClust, kTab>(L, rec, orig, C, fd.lofs, sc, tid, ps, key, nbh, full, lmask);
             }
@@ -1343,7 +1355,7 @@ __device__ __forceinline__ void split_sweeps(const SweepParams<Real> &P, const S
         // member g's records: every G-th of the length-sorted order (the same
         // mix of clause lengths for all members), stored as one contiguous run
         const PhiloxSweep ps = philox_sweep_consts(tlo, (uint32_t)c.b, thi, c.key);
-        const StepCounter sc{L.cnt + 62, (int)s * c.steps, 1, __builtin_amdgcn_readfirstlane(tid / kWave),
+        const StepCounter sc{(int)s * c.steps, 1, __builtin_amdgcn_readfirstlane(tid / kWave),
                              NT / kWave};
         const int cnt = c.sample ? clause_phase<true, kClust, kBucketPush>(L, c.rec + c.c_lo, c.orig + c.c_lo, c.c_hi - c.c_lo,
                                                               c.bnd, sc, tid, ps, c.key, c.nbh, c.full, c.lmask)
