@@ -713,15 +713,20 @@ __device__ __forceinline__ void rec_load(const RecView &rv, int first, int lane,
 // simply take more steps and all of them reach the end of the clause phase
 // together (fixed shares left the youngest waves running alone at the end of
 // every clause phase).  The accumulators are exact integers, so which wave
-// takes which step does not change any result.  The counter runs on across
-// the sweeps of an item: every wave takes exactly one step number past the
-// last one per sweep, so sweep s of an item owns the numbers
-// [s (T + W), (s + 1) (T + W)) for T steps and W waves.
+// takes which step does not change any result.  The counter hands out pairs
+// of consecutive steps (2j, 2j + 1): a wave goes to the counter only every
+// other step, so half as often waits for the add's result, whose wait also
+// covers the previous clause's accumulator atomics.  The counter runs on
+// across the sweeps of an item.  Of T steps (ceil(T/2) pairs) and W waves,
+// every wave takes one pair past the last one per sweep, except, for odd T,
+// the wave holding the last pair, whose second number T already ends its
+// clause phase: sweep s of an item owns the pair numbers [s P, (s + 1) P)
+// with P = ceil(T/2) + W - (T mod 2).
 // With dyn == 0 the steps are dealt round-robin instead (step k to wave
 // k mod W, no counter): better when another workgroup shares the CU and
 // fills the SIMDs while this one waits at its barrier.
 struct StepCounter {
-    int base;                    // first number of this sweep
+    int base;                    // first pair number of this sweep
     int dyn;                     // 1: take steps from the counter; 0: round-robin
     int wave, nw;
 };
@@ -768,7 +773,8 @@ __device__ __forceinline__ int lds_fetch_add1_wave(uint32_t one) {
 template <int kAddr>
 __device__ __forceinline__ int take_step(const StepCounter &sc, int prev) {
     if (!sc.dyn) return prev < 0 ? sc.wave : prev + sc.nw;
-    return lds_fetch_add1_wave<kAddr>(1u) - sc.base;
+    if (prev >= 0 && (prev & 1) == 0) return prev + 1;     // the second step of the pair
+    return 2 * (lds_fetch_add1_wave<kAddr>(1u) - sc.base);
 }
 
 // The steps [olo, ohi) of the run [lo, hi) of clauses of length LEN.  `k`
@@ -845,11 +851,11 @@ __device__ __forceinline__ int clause_phase_nb(const PushLds &L, const RecView &
     return cnt;
 }
 
-// step numbers one sweep of a range consumes: T steps plus one per wave
+// counter numbers (pairs of steps) one sweep of a range consumes
 __device__ __forceinline__ int sweep_step_numbers(const int32_t (&bnd)[8], int NT) {
     int32_t o[8];
     run_steps(bnd, o);
-    return o[7] + NT / kWave;
+    return (o[7] + 1) / 2 + NT / kWave - (o[7] & 1);
 }
 
 template <bool kSample, bool kClust, int kTab>
